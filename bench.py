@@ -1,0 +1,185 @@
+"""Benchmark: vehicle-steps per second of the LPSim vehicle update on one MI355X.
+
+Workload (the paper's single-GPU regional case at its published size, on
+synthetic stand-ins for the SF Bay network and SFCTA demand): planar road
+graph of 225,150 nodes and 550,000 directed edges, 2,820,000 routed trips over
+a two-peak 3 h morning profile, dt = 0.5 s, horizon 28,800 steps.
+
+A "step" is one simulation time step of every vehicle (move, resolve, lane
+change, commit).  value = vehicle-steps / s over the timed steps (a
+vehicle-step is one vehicle active at the start of a step), inputs resident in
+device memory.  The roofline entry prices the dominant kernel's measured
+algorithmic bytes against the MI355X HBM peak; `cpu_baseline` times the plain
+CPU oracle on a bounded prefix of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of the move kernel per active vehicle-step, besides the
+# measured lane-map / next-edge bytes (scan_bytes counter):
+#   slot state read: x, v, edge, meta (16) + edge record (16)
+#   slot state write: x, v, meta (12)
+MOVE_FIXED_BYTES = 16 + 16 + 12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2406_08496_amd import synth
+
+    if name == "regional":
+        return synth.regional(), 48
+    if name == "tiny":
+        return synth.tiny_grid(), 12
+    if name.startswith("regional:"):
+        return synth.regional(float(name.split(":")[1])), 48
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(inst, n_bins, budget_s):
+    """The oracle as it is, single thread, from step 0 until the budget runs out."""
+    import oracle
+
+    o = oracle.OracleSim(n_bins=n_bins).load(inst)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s and steps < inst.n_steps:
+        o.step(100)
+        steps += 100
+    el = time.perf_counter() - t0
+    c = o.counters()
+    return {"value": c["vehicle_steps"] / el, "unit": "vehicle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"steps 0..{steps} of the same workload ({c['vehicle_steps']} vehicle-steps, "
+                      f"{el:.1f} s, single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: full horizon)")
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="regional")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--blocks", type=int, default=2048)
+    ap.add_argument("--graph-steps", type=int, default=32)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_08496_amd.lpsim import Simulator
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    inst, n_bins = make_workload(args.workload)
+    K = args.steps if args.steps is not None else inst.n_steps
+    W = args.warmup
+    log(f"workload {inst.name}: {inst.n_nodes} nodes, {inst.n_edges} edges, {inst.n_trips} trips, "
+        f"{int(inst.route_off[-1])} route entries; generated in {time.perf_counter() - t:.1f} s")
+
+    t = time.perf_counter()
+    sim = Simulator(n_bins=n_bins)
+    sim.set_launch(args.block, args.blocks, args.graph_steps)
+    sim.load(inst)
+    log(f"loaded in {time.perf_counter() - t:.1f} s")
+    stream = torch.cuda.current_stream()
+    # warm-up steps (graph capture, caches), then rewind to step 0
+    snap0 = sim.save_state()
+    if W:
+        sim.step(W, stream=stream)
+        torch.cuda.synchronize()
+    sim.restore_state(snap0)
+
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    sim.step(K, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    c = sim.counters()
+    vsteps = c["vehicle_steps"]
+    value = vsteps / (ms / 1e3)
+    log(f"timed {K} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), {vsteps} vehicle-steps, "
+        f"arrived {c['arrived']}/{inst.n_trips}, active {c['active']}, watchdog {c['watchdog']}")
+
+    out = {
+        "metric": "vehicle-steps/sec at 2.8M trips",
+        "value": value,
+        "unit": "vehicle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded planar graph + gravity demand standing in for SF Bay / SFCTA)",
+        "config": {"workload": inst.name, "nodes": inst.n_nodes, "edges": inst.n_edges,
+                   "trips": inst.n_trips, "dt": 0.5, "horizon_steps": inst.n_steps,
+                   "block": args.block, "blocks": args.blocks, "graph_steps": args.graph_steps},
+        "trips_per_s": c["arrived"] / (ms / 1e3),
+        "arrived": c["arrived"],
+        "vehicle_steps": vsteps,
+    }
+
+    if not args.no_roofline:
+        # same K steps from the same state, kernels launched one by one with a
+        # HIP event pair around each on the work stream
+        sim.restore_state(snap0)
+        sim.set_timing(True)
+        sim.step(K, stream=stream)
+        torch.cuda.synchronize()
+        times = sim.kernel_times()
+        c2 = sim.counters()
+        sim.set_timing(False)
+        dom = max(times, key=lambda k: times[k][0])
+        alg_bytes = MOVE_FIXED_BYTES * c2["vehicle_steps"] + c2["scan_bytes"]
+        mv_ms, mv_n = times["move"]
+        achieved = alg_bytes / (mv_ms / 1e3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_move", "achieved": achieved,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": None,
+                           "bytes_per_launch": alg_bytes / max(mv_n, 1),
+                           "avg_launch_us": mv_ms * 1e3 / max(mv_n, 1)}
+        out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
+                                "avg_us": (v[0] * 1e3 / v[1]) if v[1] else None}
+                            for k, v in times.items()}
+        out["dominant_kernel"] = dom
+        log("kernel times:", json.dumps(out["kernel_ms"]))
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget)
+        log("cpu baseline:", json.dumps(out["cpu_baseline"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

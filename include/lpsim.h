@@ -1,0 +1,239 @@
+/*
+ * lpsim.h -- C ABI of the MI355X (gfx950) LPSim vehicle-propagation library.
+ *
+ * The library advances a regional microscopic traffic simulation one time
+ * step at a time on one GPU, as described in Jiang, Sengupta, Demmel,
+ * Williams, "Large Scale Multi-GPU Based Parallel Traffic Simulation for
+ * Accelerated Traffic Assignment and Propagation":
+ *   - inputs are a road network (per edge: lanes, length, upstream and
+ *     downstream node; Section 3.1, network data) and routed demand (per trip:
+ *     departure time and full route; Section 3.1, vehicle data);
+ *   - every step updates all vehicles from the previous step's state only
+ *     (Section 3.1, vehicle-dynamics equation; Algorithm 1): leader search on
+ *     the byte-per-metre lane map, IDM car following, stop-line waiting and
+ *     exclusive entry at intersections, departures, mandatory lane change with
+ *     gap acceptance;
+ *   - outputs are vehicle positions and speeds (Algorithm 1 output) and
+ *     per-edge travel times (abstract: travel-time estimation).
+ *
+ * Conventions for every function:
+ *   - returns LPSIM_OK (0) or a negative status; nothing throws;
+ *   - on error, lpsim_last_error(ctx) holds a one-line description;
+ *   - pointers documented "host" are read during the call only and remain
+ *     owned by the caller; the library copies what it keeps;
+ *   - a context is used by one host thread at a time;
+ *   - after an LPSIM_EDEVICE error the context is poisoned: only
+ *     lpsim_last_error and lpsim_destroy remain valid.
+ *
+ * Batches: lpsim_batch_load places several independent scenarios in one
+ * context; every call below then covers all of them at once (arrays are the
+ * scenarios' arrays concatenated in scenario order).  lpsim_load_network +
+ * lpsim_load_trips is the batch of one.
+ */
+#ifndef LPSIM_H
+#define LPSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LPSIM_OK 0
+#define LPSIM_EINVAL (-1)    /* bad argument or input data */
+#define LPSIM_ENOMEM (-2)    /* device or host allocation failed */
+#define LPSIM_EDEVICE (-3)   /* HIP runtime error; context poisoned */
+#define LPSIM_ESTATE (-4)    /* call out of order (e.g. step before load) */
+#define LPSIM_ECAPACITY (-5) /* instance exceeds a documented size limit */
+
+/* Vehicle status values reported by lpsim_get_vehicles. */
+#define LPSIM_WAITING 0
+#define LPSIM_ACTIVE 1
+#define LPSIM_ARRIVED 2
+
+/* No leader: jump to the edge speed limit (Algorithm 1, "v <- v_free"). */
+#define LPSIM_FREE_JUMP 0
+/* No leader: IDM free-road acceleration a(1 - (v/v0)^4). */
+#define LPSIM_FREE_IDM 1
+
+typedef struct lpsim_ctx lpsim_ctx;
+
+/*
+ * Model constants (Section 3.1 notation table).  All lengths in metres, times
+ * in seconds, speeds in m/s; the simulation state is binary32.
+ *   dt        time step (the paper's T as a step size; it states no value)
+ *   a, b      IDM acceleration potential and comfortable braking
+ *   s0, T     IDM standstill gap and desired time headway
+ *   delta     IDM exponent; only 4 is supported
+ *   veh_len   vehicle length L (enters gaps; a vehicle marks one cell)
+ *   x0        mandatory lane change starts x0 before the edge end
+ *   g_a, g_b  desired lead / lag gaps for a lane change
+ *   alpha_i, alpha_a, alpha_b  anticipation times (own, lead, lag)
+ *   bin_seconds   statistics bin width; must be a whole number of steps
+ *   n_bins    number of statistics bins; later events fall in the last bin
+ *   seed      seed of the hashed lane-change draws
+ *   free_mode LPSIM_FREE_JUMP or LPSIM_FREE_IDM
+ *   lane_change   1 to enable mandatory lane changes, 0 to disable
+ */
+typedef struct {
+    float dt, a, b, s0, T, veh_len, x0, g_a, g_b, alpha_i, alpha_a, alpha_b;
+    double bin_seconds;
+    int32_t delta;
+    int32_t n_bins;
+    uint64_t seed;
+    int32_t free_mode;
+    int32_t lane_change;
+} lpsim_params;
+
+typedef struct {
+    int64_t step;          /* steps taken since lpsim_load_trips */
+    int64_t active;        /* vehicles on the road now */
+    int64_t waiting;       /* trips not yet departed */
+    int64_t arrived;       /* trips finished */
+    int64_t vehicle_steps; /* sum over steps of the vehicles active at the step's start */
+    int64_t transfers;     /* edge-to-edge moves */
+    int64_t departures;    /* trips that entered the network */
+    int64_t claims_lost;   /* entry requests that lost to a lower trip id */
+    int64_t lc_attempts;   /* lane-change draws that succeeded */
+    int64_t lc_accepts;    /* lane changes carried out */
+    int64_t watchdog;      /* consecutive steps with vehicles but no entry/exit */
+    int64_t scan_bytes;    /* lane-map and next-edge bytes read by the move phase */
+} lpsim_counters;
+
+/* Create a context.  `p` (host) is copied and validated: every length, time
+ * and rate > 0 (gaps and alphas >= 0), delta == 4, bin_seconds/dt integral.
+ * Errors: EINVAL, ENOMEM, EDEVICE (no usable GPU). */
+int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out);
+
+/* Release every device and host resource.  Accepts NULL. */
+void lpsim_destroy(lpsim_ctx *ctx);
+
+/* Optional: route device allocations through caller callbacks (for example a
+ * framework's caching allocator).  Must be called before any load.  `alloc`
+ * returns device memory of at least `bytes` bytes or NULL. */
+int32_t lpsim_set_allocator(lpsim_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                            void (*release)(void *ptr, void *user), void *user);
+
+/* Load the road network (Section 3.1, network data and lane map).
+ *   n_nodes            number of intersections
+ *   node_xy            host, 2*n_nodes floats (x, y) or NULL; when given, edges
+ *                      are stored in recursive-coordinate-bisection order of
+ *                      their upstream node (memory locality only; results do
+ *                      not depend on it)
+ *   n_edges            number of directed edges; edge e runs src[e] -> dst[e]
+ *   length_m           host, edge length; the edge has ceil(length) one-metre cells
+ *   lanes              host, 1..8 lanes per edge
+ *   speed_limit_mps    host, 0 < v0 <= 254 (the lane-map byte holds the speed)
+ * Each edge must have at least ceil(veh_len + s0) + 1 and at most 65535 cells;
+ * a node may have at most 255 out-edges.  Replaces any loaded network and
+ * discards loaded trips.  Errors: EINVAL, ENOMEM, ECAPACITY (lane map over
+ * 4 GiB), EDEVICE. */
+int32_t lpsim_load_network(lpsim_ctx *ctx, int32_t n_nodes, const float *node_xy,
+                           int32_t n_edges, const int32_t *src, const int32_t *dst,
+                           const float *length_m, const uint8_t *lanes,
+                           const float *speed_limit_mps);
+
+/* Load routed demand (Section 3.1, vehicle data).  Trip id = array index.
+ *   depart_step    host, n_trips departure steps (>= 0); any order
+ *   route_offsets  host, n_trips+1 offsets into route_edges, route_offsets[0] = 0
+ *   route_edges    host, each trip's edges; non-empty and contiguous
+ *                  (dst of one edge = src of the next)
+ * Resets the clock to step 0, the lane map, the statistics and the counters.
+ * Errors: ESTATE (no network), EINVAL, ENOMEM, ECAPACITY (more than 2^31-2
+ * trips or 2^32-2 route entries), EDEVICE. */
+int32_t lpsim_load_trips(lpsim_ctx *ctx, int64_t n_trips, const int32_t *depart_step,
+                         const int64_t *route_offsets, const int32_t *route_edges);
+
+/* Load n_scen independent scenarios into one context (batched execution).
+ * Arrays are the scenarios' own arrays concatenated; node, edge and trip ids
+ * inside each scenario's arrays are LOCAL to that scenario.
+ *   node_off[n_scen+1], edge_off[n_scen+1], trip_off[n_scen+1]: host prefix sums
+ *   node_xy        host, 2 floats per node, or NULL
+ *   src, dst, length_m, lanes, speed_limit_mps: host, per edge
+ *   depart_step    host, per trip
+ *   route_offsets  host, per scenario trip_count+1 entries, each scenario's
+ *                  starting at 0 (total n_trips + n_scen entries)
+ *   route_edges    host, concatenated routes (local edge ids)
+ *   seeds          host, per-scenario lane-change seed, or NULL for params.seed
+ * A scenario's result equals what a context holding only that scenario
+ * produces.  Errors as lpsim_load_network + lpsim_load_trips. */
+int32_t lpsim_batch_load(lpsim_ctx *ctx, int32_t n_scen, const int32_t *node_off,
+                         const int32_t *edge_off, const int64_t *trip_off,
+                         const float *node_xy, const int32_t *src, const int32_t *dst,
+                         const float *length_m, const uint8_t *lanes,
+                         const float *speed_limit_mps, const int32_t *depart_step,
+                         const int64_t *route_offsets, const int32_t *route_edges,
+                         const uint64_t *seeds);
+
+/* Advance n_steps time steps (Algorithm 1 per vehicle, synchronous update).
+ *   hip_stream   a hipStream_t to order the work on, or NULL: then the call
+ *                runs on an internal stream and returns after the work is done.
+ * With a stream the call only enqueues; the caller synchronises the stream.
+ * Errors: ESTATE (no trips loaded), EINVAL (n_steps < 0), EDEVICE. */
+int32_t lpsim_step(lpsim_ctx *ctx, int32_t n_steps, void *hip_stream);
+
+/* Per-edge statistics, in input edge order (host buffers, caller-owned).
+ *   tt_sum_steps[E]  sum over completed traversals of (exit step - entry step)
+ *   n_exits[E]       number of completed traversals
+ *   inflow_bin[E*B]  entries by entry bin (bin = step*dt / bin_seconds)
+ *   exits_bin[E*B], tt_sum_bin[E*B]  completed traversals and their travel
+ *                    times, binned by ENTRY step
+ *   occ_steps_bin[E*B]  vehicle-steps spent on the edge per bin (density),
+ *                    including vehicles still on it
+ * Mean travel time of edge e in seconds = tt_sum_steps[e] * dt / n_exits[e].
+ * Binned pointers may be NULL.  Waits for all queued work.  Errors: ESTATE,
+ * EDEVICE. */
+int32_t lpsim_edge_stats(lpsim_ctx *ctx, int64_t *tt_sum_steps, int32_t *n_exits,
+                         int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
+                         int64_t *occ_steps_bin);
+
+/* Vehicle state per trip, trip order, input edge ids (host buffers of n_trips,
+ * any may be NULL): edge (-1 unless active), lane, cell = floor(x) (-1 unless
+ * active), x (m from the edge start) and v (m/s) (0 unless active),
+ * arrival_step (-1 until arrived), status (LPSIM_WAITING/ACTIVE/ARRIVED).
+ * Waits for all queued work.  Errors: ESTATE, EDEVICE. */
+int32_t lpsim_get_vehicles(lpsim_ctx *ctx, int32_t *edge, uint8_t *lane, int32_t *cell,
+                           float *x, float *v, int32_t *arrival_step, uint8_t *status);
+
+/* Counters (see lpsim_counters).  Waits for all queued work. */
+int32_t lpsim_get_counters(lpsim_ctx *ctx, lpsim_counters *out);
+
+/* Test hook: a blocked edge accepts no entries, as a full downstream edge
+ * (Section 3.1 Remarks, intersection modelling).  Input edge id. */
+int32_t lpsim_block_edge(lpsim_ctx *ctx, int32_t edge, int32_t on);
+
+/* Launch shape: threads per block (64..1024, multiple of 64), blocks per
+ * vehicle kernel (multiple of 8, up to 8192), steps captured per HIP graph
+ * (>= 1; 0 launches kernels one by one).  Results do not depend on these. */
+int32_t lpsim_set_launch(lpsim_ctx *ctx, int32_t block_size, int32_t n_blocks,
+                         int32_t graph_steps);
+
+/* Kernel timing for measurement: when on, lpsim_step launches kernels one by
+ * one and records a HIP event pair around each on the work stream;
+ * lpsim_kernel_times then returns the summed milliseconds and launch counts
+ * of the phases (0 move, 1 resolve, 2 lane change, 3 commit, 4 compact).
+ * Turning it on or off resets the sums. */
+int32_t lpsim_set_timing(lpsim_ctx *ctx, int32_t on);
+int32_t lpsim_kernel_times(lpsim_ctx *ctx, double *ms_out, int64_t *launches_out,
+                           int32_t n_phases);
+
+/* Checkpoint: size of a snapshot, save into a caller buffer, restore from it.
+ * A restored context continues bit-identically.  Errors: ESTATE, EINVAL
+ * (buffer too small or from another instance), EDEVICE. */
+int32_t lpsim_state_size(lpsim_ctx *ctx, size_t *bytes);
+int32_t lpsim_save_state(lpsim_ctx *ctx, void *host_buf, size_t bytes);
+int32_t lpsim_restore_state(lpsim_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Derived constants: 0 -> entry window W (cells), 1 -> look-ahead D (cells)
+ * of scenario 0, 2 -> steps per statistics bin. */
+int32_t lpsim_query(const lpsim_ctx *ctx, int32_t which);
+
+/* Last error text of this context ("" if none).  Accepts NULL. */
+const char *lpsim_last_error(const lpsim_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPSIM_H */

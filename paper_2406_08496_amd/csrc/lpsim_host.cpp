@@ -1,0 +1,1058 @@
+// lpsim_host.cpp -- host side of the C ABI declared in include/lpsim.h:
+// validation, device layout, HIP graph capture of the step kernels, read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lpsim.h"
+#include "lpsim_dev.h"
+
+using namespace lpsim;
+
+namespace {
+
+constexpr int N_PHASES = 5;
+constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
+
+}  // namespace
+
+struct lpsim_ctx {
+    lpsim_params P{};
+    Params dp{};
+    int device = 0;
+    hipStream_t own = nullptr;
+    hipStream_t last = nullptr;
+    std::string err;
+    bool poisoned = false;
+    void *(*ualloc)(size_t, void *) = nullptr;
+    void (*ufree)(void *, void *) = nullptr;
+    void *uuser = nullptr;
+    std::vector<void *> net_allocs, trip_allocs;
+
+    // network (all scenarios)
+    int32_t n_scen = 0;
+    std::vector<int32_t> edge_off, node_off;   // per scenario, global ranges
+    std::vector<int32_t> look;                 // per scenario lookahead D
+    std::vector<int32_t> ext_of_int;           // internal edge -> global input edge id
+    std::vector<int32_t> int_of_ext;           // global input edge id -> internal
+    std::vector<int32_t> src_g, dst_g;         // global input edge order, local node ids
+    std::vector<uint32_t> aux_h;               // internal order
+    int32_t n_edges = 0;
+    uint64_t map_bytes = 0;
+    uint32_t n_lane_slots = 0;
+    bool have_net = false;
+
+    // trips
+    int64_t n_trips = 0;
+    std::vector<int64_t> trip_off;
+    bool have_trips = false;
+    uint32_t slot_cap = 0;
+
+    Dev d{};
+
+    // launch shape
+    int threads = 256;
+    int blocks = 2048;
+    int commit_blocks = 32;
+    int graph_steps = 32;
+    hipGraphExec_t g_full = nullptr, g_one = nullptr;
+    int direct_since_compact = 0;
+
+    // timing
+    bool timing = false;
+    double ms[N_PHASES] = {0};
+    int64_t launches[N_PHASES] = {0};
+    std::vector<hipEvent_t> ev;   // begin/end pairs
+    std::vector<int> ev_phase;    // phase of each recorded pair
+    int ev_used = 0;              // pairs recorded and not yet harvested
+};
+
+// ---------------------------------------------------------------------------
+// errors
+
+static int32_t fail(lpsim_ctx *c, int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) {
+        c->err = buf;
+        if (code == LPSIM_EDEVICE) c->poisoned = true;
+    }
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((c), LPSIM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// memory
+
+static void *dev_alloc(lpsim_ctx *c, size_t bytes, std::vector<void *> &owner) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (c->ualloc) {
+        p = c->ualloc(bytes, c->uuser);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) owner.push_back(p);
+    return p;
+}
+
+static void dev_free_all(lpsim_ctx *c, std::vector<void *> &owner) {
+    for (void *p : owner) {
+        if (c->ufree) c->ufree(p, c->uuser);
+        else (void)hipFree(p);
+    }
+    owner.clear();
+}
+
+static void drop_graphs(lpsim_ctx *c) {
+    if (c->g_full) (void)hipGraphExecDestroy(c->g_full);
+    if (c->g_one) (void)hipGraphExecDestroy(c->g_one);
+    c->g_full = c->g_one = nullptr;
+}
+
+static int32_t sync_all(lpsim_ctx *c) {
+    if (c->last) HIPCHK(c, hipStreamSynchronize(c->last));
+    HIPCHK(c, hipStreamSynchronize(c->own));
+    return LPSIM_OK;
+}
+
+template <class T>
+static int32_t upload(lpsim_ctx *c, T *&dst, const T *src, size_t n, std::vector<void *> &owner) {
+    dst = (T *)dev_alloc(c, n * sizeof(T), owner);
+    if (!dst) return fail(c, LPSIM_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
+    if (n) HIPCHK(c, hipMemcpy(dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return LPSIM_OK;
+}
+
+template <class T>
+static int32_t alloc_n(lpsim_ctx *c, T *&dst, size_t n, std::vector<void *> &owner) {
+    dst = (T *)dev_alloc(c, n * sizeof(T), owner);
+    if (!dst) return fail(c, LPSIM_ENOMEM, "device allocation of %zu bytes failed", n * sizeof(T));
+    return LPSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// recursive coordinate bisection of nodes: a locality order
+
+static void rcb(std::vector<int32_t> &idx, size_t lo, size_t hi, const float *xy, size_t leaf) {
+    if (hi - lo <= leaf) return;
+    float xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (size_t i = lo; i < hi; ++i) {
+        const float x = xy[2 * (size_t)idx[i]], y = xy[2 * (size_t)idx[i] + 1];
+        xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+        ymin = std::min(ymin, y); ymax = std::max(ymax, y);
+    }
+    const int axis = (xmax - xmin) >= (ymax - ymin) ? 0 : 1;
+    const size_t mid = lo + (hi - lo) / 2;
+    std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi,
+                     [&](int32_t a, int32_t b) {
+                         const float pa = xy[2 * (size_t)a + axis], pb = xy[2 * (size_t)b + axis];
+                         return pa < pb || (pa == pb && a < b);
+                     });
+    rcb(idx, lo, mid, xy, leaf);
+    rcb(idx, mid, hi, xy, leaf);
+}
+
+// ---------------------------------------------------------------------------
+// network
+
+static void release_trips(lpsim_ctx *c) {
+    drop_graphs(c);
+    dev_free_all(c, c->trip_allocs);
+    c->have_trips = false;
+    c->n_trips = 0;
+}
+
+static void release_net(lpsim_ctx *c) {
+    release_trips(c);
+    dev_free_all(c, c->net_allocs);
+    c->have_net = false;
+}
+
+struct NetIn {
+    int32_t n_scen;
+    const int32_t *node_off, *edge_off;
+    const float *node_xy;
+    const int32_t *src, *dst;
+    const float *length;
+    const uint8_t *lanes;
+    const float *speed;
+};
+
+static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
+    const lpsim_params &P = c->P;
+    const int32_t S = in.n_scen;
+    if (S < 1) return fail(c, LPSIM_EINVAL, "need at least one scenario");
+    if (in.node_off[0] != 0 || in.edge_off[0] != 0) return fail(c, LPSIM_EINVAL, "offsets must start at 0");
+    for (int32_t s = 0; s < S; ++s) {
+        if (in.node_off[s + 1] <= in.node_off[s] || in.edge_off[s + 1] <= in.edge_off[s])
+            return fail(c, LPSIM_EINVAL, "scenario %d has no nodes or no edges", s);
+    }
+    const int32_t E = in.edge_off[S];
+    const int32_t W = c->dp.W;
+    std::vector<int32_t> look(S);
+    std::vector<int32_t> cells(E);
+    for (int32_t s = 0; s < S; ++s) {
+        const int32_t nn = in.node_off[s + 1] - in.node_off[s];
+        double vmax = 0.0;
+        for (int32_t e = in.edge_off[s]; e < in.edge_off[s + 1]; ++e) {
+            if (in.src[e] < 0 || in.src[e] >= nn || in.dst[e] < 0 || in.dst[e] >= nn)
+                return fail(c, LPSIM_EINVAL, "edge %d: node id out of range", e);
+            if (in.lanes[e] < 1 || in.lanes[e] > 8)
+                return fail(c, LPSIM_EINVAL, "edge %d: lanes must be 1..8", e);
+            if (!(in.speed[e] > 0.0f && in.speed[e] <= 254.0f))
+                return fail(c, LPSIM_EINVAL, "edge %d: speed limit must be in (0, 254]", e);
+            if (!(in.length[e] > 0.0f)) return fail(c, LPSIM_EINVAL, "edge %d: length must be > 0", e);
+            const double cl = std::ceil((double)in.length[e]);
+            if (cl < (double)(W + 1) || cl > 65535.0)
+                return fail(c, LPSIM_EINVAL, "edge %d: %g cells, need %d..65535", e, cl, W + 1);
+            cells[e] = (int32_t)cl;
+            vmax = std::max(vmax, (double)in.speed[e]);
+        }
+        // leader look-ahead: at least 2*dt*v (the paper's bound), extended to
+        // the IDM desired gap s0 + T*v at the scenario's top speed
+        const double reach = 2.0 * (double)P.dt * vmax;
+        const double desired = (double)P.s0 + (double)P.T * vmax;
+        const double Dd = std::ceil((double)P.veh_len + std::max(reach, desired));
+        if (Dd > 255.0) return fail(c, LPSIM_ECAPACITY, "look-ahead of %g cells exceeds 255", Dd);
+        look[s] = (int32_t)Dd;
+    }
+
+    // internal order: per scenario, RCB order of the upstream node, then id
+    std::vector<int32_t> ext_of_int(E), int_of_ext(E);
+    for (int32_t s = 0; s < S; ++s) {
+        const int32_t e0 = in.edge_off[s], e1 = in.edge_off[s + 1];
+        const int32_t nn = in.node_off[s + 1] - in.node_off[s];
+        std::vector<int32_t> order(e1 - e0);
+        std::iota(order.begin(), order.end(), e0);
+        if (in.node_xy) {
+            std::vector<int32_t> nodes(nn);
+            std::iota(nodes.begin(), nodes.end(), 0);
+            rcb(nodes, 0, nodes.size(), in.node_xy + 2 * (size_t)in.node_off[s], 1024);
+            std::vector<int32_t> rank(nn);
+            for (int32_t i = 0; i < nn; ++i) rank[nodes[i]] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                return rank[in.src[a]] < rank[in.src[b]];
+            });
+        }
+        for (int32_t i = 0; i < e1 - e0; ++i) {
+            ext_of_int[e0 + i] = order[i];
+            int_of_ext[order[i]] = e0 + i;
+        }
+    }
+
+    // out-edge rank (by input id) and out-degree per edge, per scenario
+    std::vector<uint32_t> rank_e(E), deg_e(E);
+    for (int32_t s = 0; s < S; ++s) {
+        const int32_t nn = in.node_off[s + 1] - in.node_off[s];
+        std::vector<int32_t> deg(nn, 0);
+        for (int32_t e = in.edge_off[s]; e < in.edge_off[s + 1]; ++e) rank_e[e] = deg[in.src[e]]++;
+        for (int32_t e = in.edge_off[s]; e < in.edge_off[s + 1]; ++e) {
+            deg_e[e] = deg[in.src[e]];
+            if (deg_e[e] > 255) return fail(c, LPSIM_ECAPACITY, "node with more than 255 out-edges");
+        }
+    }
+
+    std::vector<uint4> rec(E);
+    std::vector<uint32_t> aux(E);
+    std::vector<int32_t> escen(E);
+    uint64_t off = 0;
+    uint64_t slot = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int32_t i = in.edge_off[s]; i < in.edge_off[s + 1]; ++i) {
+            const int32_t e = ext_of_int[i];
+            const uint32_t C = (uint32_t)cells[e], nl = in.lanes[e];
+            float v0 = in.speed[e];
+            uint32_t v0b;
+            std::memcpy(&v0b, &v0, 4);
+            rec[i] = make_uint4((uint32_t)off, C | (nl << 16) | ((uint32_t)look[s] << 24), v0b, (uint32_t)slot);
+            aux[i] = rank_e[e] | (deg_e[e] << 8);
+            escen[i] = s;
+            off += (uint64_t)C * nl;
+            slot += nl;
+            if (off > 0xffffff00ull) return fail(c, LPSIM_ECAPACITY, "lane map exceeds 4 GiB");
+        }
+    }
+
+    release_net(c);
+    c->n_scen = S;
+    c->edge_off.assign(in.edge_off, in.edge_off + S + 1);
+    c->node_off.assign(in.node_off, in.node_off + S + 1);
+    c->look = look;
+    c->ext_of_int = ext_of_int;
+    c->int_of_ext = int_of_ext;
+    c->src_g.assign(in.src, in.src + E);
+    c->dst_g.assign(in.dst, in.dst + E);
+    c->aux_h = aux;
+    c->n_edges = E;
+    c->map_bytes = off;
+    c->n_lane_slots = (uint32_t)slot;
+
+    Dev &d = c->d;
+    int32_t rc;
+    const uint4 *edge_d;
+    if ((rc = upload(c, *(uint4 **)&edge_d, rec.data(), rec.size(), c->net_allocs))) return rc;
+    d.edge = edge_d;
+    if ((rc = upload(c, d.aux, aux.data(), aux.size(), c->net_allocs))) return rc;
+    const int32_t *escen_d;
+    if ((rc = upload(c, *(int32_t **)&escen_d, escen.data(), escen.size(), c->net_allocs))) return rc;
+    d.escen = escen_d;
+    if ((rc = alloc_n(c, d.map, off + 256, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.claims, (size_t)slot, c->net_allocs))) return rc;
+    const size_t nb = (size_t)E * (size_t)c->dp.n_bins;
+    if ((rc = alloc_n(c, d.n_exits, (size_t)E, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.tt_sum, (size_t)E, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.inflow_bin, nb, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.exits_bin, nb, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.tt_bin, nb, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.occ_bin, nb, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.partial, (size_t)MAX_BLOCKS * NPART, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.ctrl, 1, c->net_allocs))) return rc;
+    HIPCHK(c, hipMemset(d.map, 0xff, off + 256));
+    HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)slot * 4));
+    c->have_net = true;
+    return LPSIM_OK;
+}
+
+struct TripIn {
+    const int64_t *trip_off;       // per scenario, n_scen+1
+    const int32_t *depart;         // global
+    const int64_t *route_offsets;  // per scenario (count+1 each), concatenated
+    const int32_t *route_edges;    // concatenated, local edge ids
+    const uint64_t *seeds;
+};
+
+static int32_t reset_run_state(lpsim_ctx *c) {
+    Dev &d = c->d;
+    const size_t E = (size_t)c->n_edges, nb = E * (size_t)c->dp.n_bins;
+    const size_t N = (size_t)c->n_trips;
+    HIPCHK(c, hipMemset(d.map, 0xff, c->map_bytes + 256));
+    HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
+    HIPCHK(c, hipMemset(d.n_exits, 0, E * 4));
+    HIPCHK(c, hipMemset(d.tt_sum, 0, E * 8));
+    HIPCHK(c, hipMemset(d.inflow_bin, 0, nb * 4));
+    HIPCHK(c, hipMemset(d.exits_bin, 0, nb * 4));
+    HIPCHK(c, hipMemset(d.tt_bin, 0, nb * 8));
+    HIPCHK(c, hipMemset(d.occ_bin, 0, nb * 8));
+    HIPCHK(c, hipMemset(d.partial, 0, (size_t)MAX_BLOCKS * NPART * 8));
+    HIPCHK(c, hipMemset(d.status, 0, N + 1));
+    HIPCHK(c, hipMemset(d.arrival, 0xff, (N + 1) * 4));
+    HIPCHK(c, hipMemset(d.dclaim, 0, N + 1));
+    Ctrl ct{};
+    ct.wait_lo_next = 0xffffffffu;
+    HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
+    // the blocked flags survive a reload of trips
+    HIPCHK(c, hipMemcpy(d.aux, c->aux_h.data(), c->aux_h.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipDeviceSynchronize());
+    return LPSIM_OK;
+}
+
+static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
+    if (!c->have_net) return fail(c, LPSIM_ESTATE, "load a network first");
+    const int32_t S = c->n_scen;
+    if (in.trip_off[0] != 0) return fail(c, LPSIM_EINVAL, "trip offsets must start at 0");
+    for (int32_t s = 0; s < S; ++s)
+        if (in.trip_off[s + 1] < in.trip_off[s]) return fail(c, LPSIM_EINVAL, "trip offsets decrease");
+    const int64_t N = in.trip_off[S];
+    if (N > 0x7ffffffeLL) return fail(c, LPSIM_ECAPACITY, "more than 2^31-2 trips");
+    // validate routes and build absolute offsets
+    std::vector<uint32_t> roff((size_t)N + 1);
+    uint64_t total = 0;
+    const int64_t *ro = in.route_offsets;
+    for (int32_t s = 0; s < S; ++s) {
+        const int64_t t0 = in.trip_off[s], nt = in.trip_off[s + 1] - t0;
+        const int32_t eb = c->edge_off[s], ne = c->edge_off[s + 1] - eb;
+        if (ro[0] != 0) return fail(c, LPSIM_EINVAL, "scenario %d: route offsets must start at 0", s);
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t a = ro[t], b = ro[t + 1];
+            if (b <= a) return fail(c, LPSIM_EINVAL, "trip %lld has an empty route", (long long)(t0 + t));
+            if (in.depart[t0 + t] < 0) return fail(c, LPSIM_EINVAL, "trip %lld departs before 0", (long long)(t0 + t));
+            roff[(size_t)(t0 + t)] = (uint32_t)(total + (uint64_t)a);
+        }
+        const int64_t len = ro[nt];
+        const int32_t *re = in.route_edges + total;
+        for (int64_t t = 0; t < nt; ++t) {
+            for (int64_t j = ro[t]; j < ro[t + 1]; ++j) {
+                const int32_t e = re[j];
+                if (e < 0 || e >= ne) return fail(c, LPSIM_EINVAL, "trip %lld: edge id out of range", (long long)(t0 + t));
+                if (j > ro[t] && c->dst_g[eb + re[j - 1]] != c->src_g[eb + e])
+                    return fail(c, LPSIM_EINVAL, "trip %lld: route is not contiguous", (long long)(t0 + t));
+            }
+        }
+        total += (uint64_t)len;
+        if (total > 0xfffffff0ull) return fail(c, LPSIM_ECAPACITY, "more than 2^32-16 route entries");
+        ro += nt + 1;
+    }
+    roff[(size_t)N] = (uint32_t)total;
+    std::vector<uint32_t> route((size_t)total + 1);
+    {
+        size_t p = 0;
+        // translate local ids to internal ids scenario by scenario
+        const int64_t *ro2 = in.route_offsets;
+        for (int32_t s = 0; s < S; ++s) {
+            const int64_t nt = in.trip_off[s + 1] - in.trip_off[s];
+            const int32_t eb = c->edge_off[s];
+            const int64_t len = ro2[nt];
+            for (int64_t j = 0; j < len; ++j) route[p + (size_t)j] = (uint32_t)c->int_of_ext[eb + in.route_edges[p + (size_t)j]];
+            p += (size_t)len;
+            ro2 += nt + 1;
+        }
+        route[(size_t)total] = 0;
+    }
+    // departure order and the count of trips due by each step
+    int32_t maxdep = -1;
+    for (int64_t t = 0; t < N; ++t) maxdep = std::max(maxdep, in.depart[t]);
+    if (maxdep >= (1 << 26)) return fail(c, LPSIM_ECAPACITY, "departure step beyond 2^26");
+    std::vector<uint32_t> cnt((size_t)maxdep + 2, 0);
+    for (int64_t t = 0; t < N; ++t) cnt[(size_t)in.depart[t] + 1]++;
+    for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+    std::vector<uint32_t> order((size_t)std::max<int64_t>(N, 1));
+    {
+        std::vector<uint32_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t t = 0; t < N; ++t) order[pos[(size_t)in.depart[t]]++] = (uint32_t)t;
+    }
+    std::vector<uint32_t> dep_hi((size_t)maxdep + 2, (uint32_t)N);  // one spare entry
+    for (int32_t k = 0; k <= maxdep; ++k) dep_hi[(size_t)k] = cnt[(size_t)k + 1];
+    std::vector<uint64_t> seeds(S);
+    std::vector<uint32_t> tbase(S);
+    for (int32_t s = 0; s < S; ++s) {
+        seeds[s] = in.seeds ? in.seeds[s] : c->P.seed;
+        tbase[s] = (uint32_t)in.trip_off[s];
+    }
+
+    release_trips(c);
+    Dev &d = c->d;
+    int32_t rc;
+    c->n_trips = N;
+    c->trip_off.assign(in.trip_off, in.trip_off + S + 1);
+    const size_t cap = (size_t)std::max<int64_t>(N, 1);
+    c->slot_cap = (uint32_t)cap;
+    const uint32_t *route_d, *roff_d, *order_d, *dephi_d, *tbase_d;
+    const uint64_t *seeds_d;
+    if ((rc = upload(c, *(uint32_t **)&route_d, route.data(), route.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint32_t **)&roff_d, roff.data(), roff.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint32_t **)&order_d, order.data(), order.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint32_t **)&dephi_d, dep_hi.data(), dep_hi.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint64_t **)&seeds_d, seeds.data(), seeds.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint32_t **)&tbase_d, tbase.data(), tbase.size(), c->trip_allocs))) return rc;
+    d.route = route_d;
+    d.route_off = roff_d;
+    d.dep_order = order_d;
+    d.dep_hi = dephi_d;
+    d.n_dep_hi = maxdep + 1;
+    d.n_trips = (uint32_t)N;
+    d.scen_seed = seeds_d;
+    d.scen_tbase = tbase_d;
+    if ((rc = alloc_n(c, d.status, cap + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.arrival, cap + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.dclaim, cap + 1, c->trip_allocs))) return rc;
+    for (int b = 0; b < 2; ++b) {
+        Slots &s = d.buf[b];
+        if ((rc = alloc_n(c, s.x, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.v, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.e, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.m, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.id, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.rp, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.rend, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.ent, cap, c->trip_allocs))) return rc;
+    }
+    if ((rc = alloc_n(c, d.scl, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.sxo, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lc_list, cap, c->trip_allocs))) return rc;
+    if ((rc = reset_run_state(c))) return rc;
+    c->have_trips = true;
+    c->direct_since_compact = 0;
+    return LPSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+
+static void enqueue_step(lpsim_ctx *c, hipStream_t s) {
+    launch_move(c->d, c->blocks, c->threads, s);
+    launch_resolve(c->d, c->blocks, c->threads, s);
+    if (c->dp.lane_change) launch_lanechg(c->d, c->blocks, c->threads, s);
+    launch_commit(c->d, c->commit_blocks, c->threads, s);
+}
+
+static int32_t build_graphs(lpsim_ctx *c) {
+    drop_graphs(c);
+    for (int which = 0; which < 2; ++which) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+        const int n = which == 0 ? c->graph_steps : 1;
+        for (int t = 0; t < n; ++t) enqueue_step(c, c->own);
+        if (which == 0) launch_compact(c->d, c->blocks, c->threads, c->own);
+        HIPCHK(c, hipStreamEndCapture(c->own, &g));
+        hipGraphExec_t ex = nullptr;
+        HIPCHK(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        (which == 0 ? c->g_full : c->g_one) = ex;
+    }
+    return LPSIM_OK;
+}
+
+static int32_t harvest_events(lpsim_ctx *c) {
+    for (int i = 0; i < c->ev_used; ++i) {
+        HIPCHK(c, hipEventSynchronize(c->ev[2 * i + 1]));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        c->ms[c->ev_phase[i]] += ms;
+        c->launches[c->ev_phase[i]] += 1;
+    }
+    c->ev_used = 0;
+    return LPSIM_OK;
+}
+
+// one kernel launch bracketed by an event pair on the same stream
+static int32_t timed(lpsim_ctx *c, int phase, hipStream_t s,
+                     void (*fn)(const Dev &, int, int, hipStream_t), int blocks) {
+    if ((size_t)(c->ev_used + 1) * 2 > c->ev.size()) {
+        int32_t rc = harvest_events(c);
+        if (rc) return rc;
+    }
+    const int i = c->ev_used++;
+    c->ev_phase[i] = phase;
+    HIPCHK(c, hipEventRecord(c->ev[2 * i], s));
+    fn(c->d, blocks, c->threads, s);
+    HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], s));
+    return LPSIM_OK;
+}
+
+static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
+    int32_t rc;
+    if (c->timing) {
+        if ((rc = timed(c, 0, s, launch_move, c->blocks))) return rc;
+        if ((rc = timed(c, 1, s, launch_resolve, c->blocks))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, 2, s, launch_lanechg, c->blocks))) return rc;
+        if ((rc = timed(c, 3, s, launch_commit, c->commit_blocks))) return rc;
+    } else {
+        enqueue_step(c, s);
+    }
+    if (++c->direct_since_compact >= std::max(c->graph_steps, 32)) {
+        if (c->timing) {
+            if ((rc = timed(c, 4, s, launch_compact, c->blocks))) return rc;
+        } else {
+            launch_compact(c->d, c->blocks, c->threads, s);
+        }
+        c->direct_since_compact = 0;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LPSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// read-back helpers
+
+struct HostSlots {
+    std::vector<float> x, v;
+    std::vector<int32_t> e, ent;
+    std::vector<uint32_t> m, id;
+};
+
+static int32_t read_ctrl(lpsim_ctx *c, Ctrl &ct) {
+    HIPCHK(c, hipMemcpy(&ct, c->d.ctrl, sizeof ct, hipMemcpyDeviceToHost));
+    return LPSIM_OK;
+}
+
+static int32_t read_slots(lpsim_ctx *c, const Ctrl &ct, HostSlots &h) {
+    const uint32_t n = ct.n_slots + ct.n_new;
+    const Slots &S = c->d.buf[ct.cur];
+    h.x.resize(n); h.v.resize(n); h.e.resize(n); h.ent.resize(n); h.m.resize(n); h.id.resize(n);
+    if (!n) return LPSIM_OK;
+    HIPCHK(c, hipMemcpy(h.x.data(), S.x, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h.v.data(), S.v, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h.e.data(), S.e, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h.ent.data(), S.ent, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h.m.data(), S.m, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h.id.data(), S.id, n * 4, hipMemcpyDeviceToHost));
+    return LPSIM_OK;
+}
+
+static int32_t check_ready(lpsim_ctx *c, bool need_trips) {
+    if (!c) return LPSIM_EINVAL;
+    if (c->poisoned) return fail(c, LPSIM_EDEVICE, "context poisoned by an earlier device error: %s", c->err.c_str());
+    if (!c->have_net) return fail(c, LPSIM_ESTATE, "no network loaded");
+    if (need_trips && !c->have_trips) return fail(c, LPSIM_ESTATE, "no trips loaded");
+    HIPCHK(c, hipSetDevice(c->device));
+    return LPSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+
+extern "C" {
+
+int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out) {
+    if (!p || !out) return LPSIM_EINVAL;
+    *out = nullptr;
+    if (!(p->dt > 0 && p->a > 0 && p->b > 0 && p->s0 > 0 && p->T > 0 && p->veh_len > 0 && p->x0 > 0 &&
+          p->g_a >= 0 && p->g_b >= 0 && p->alpha_i >= 0 && p->alpha_a >= 0 && p->alpha_b >= 0 &&
+          p->bin_seconds > 0 && p->delta == 4 && p->n_bins >= 1 &&
+          (p->free_mode == LPSIM_FREE_JUMP || p->free_mode == LPSIM_FREE_IDM) &&
+          (p->lane_change == 0 || p->lane_change == 1)))
+        return LPSIM_EINVAL;
+    const double bs = p->bin_seconds / (double)p->dt;
+    const double bsr = std::nearbyint(bs);
+    if (bsr < 1.0 || std::fabs(bs - bsr) > 1e-9 || bsr > 1e9) return LPSIM_EINVAL;
+    lpsim_ctx *c = new (std::nothrow) lpsim_ctx();
+    if (!c) return LPSIM_ENOMEM;
+    c->P = *p;
+    Params &dp = c->dp;
+    dp.dt = p->dt; dp.a = p->a; dp.b = p->b; dp.s0 = p->s0; dp.T = p->T; dp.L = p->veh_len;
+    dp.x0 = p->x0; dp.g_a = p->g_a; dp.g_b = p->g_b;
+    dp.al_i = p->alpha_i; dp.al_a = p->alpha_a; dp.al_b = p->alpha_b;
+    dp.tsab = (float)(2.0 * std::sqrt((double)p->a * (double)p->b));
+    dp.half_dt = 0.5f * p->dt;
+    dp.W = (int32_t)std::ceil((double)p->veh_len + (double)p->s0);
+    dp.bin_steps = (int32_t)bsr;
+    dp.n_bins = p->n_bins;
+    dp.free_mode = p->free_mode;
+    dp.lane_change = p->lane_change;
+    c->d.p = dp;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        delete c;
+        return LPSIM_EDEVICE;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return LPSIM_EDEVICE;
+    }
+    c->ev.resize(2 * 512);
+    c->ev_phase.resize(512);
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+        }
+    }
+    *out = c;
+    return LPSIM_OK;
+}
+
+void lpsim_destroy(lpsim_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->last) (void)hipStreamSynchronize(c->last);
+    if (c->own) (void)hipStreamSynchronize(c->own);
+    release_net(c);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+}
+
+int32_t lpsim_set_allocator(lpsim_ctx *c, void *(*alloc)(size_t, void *), void (*release)(void *, void *),
+                            void *user) {
+    if (!c || (alloc == nullptr) != (release == nullptr)) return LPSIM_EINVAL;
+    if (c->have_net) return fail(c, LPSIM_ESTATE, "set the allocator before loading");
+    c->ualloc = alloc;
+    c->ufree = release;
+    c->uuser = user;
+    return LPSIM_OK;
+}
+
+int32_t lpsim_load_network(lpsim_ctx *c, int32_t n_nodes, const float *node_xy, int32_t n_edges,
+                           const int32_t *src, const int32_t *dst, const float *length_m,
+                           const uint8_t *lanes, const float *speed_limit_mps) {
+    if (!c) return LPSIM_EINVAL;
+    if (c->poisoned) return fail(c, LPSIM_EDEVICE, "context poisoned");
+    if (n_nodes <= 0 || n_edges <= 0 || !src || !dst || !length_m || !lanes || !speed_limit_mps)
+        return fail(c, LPSIM_EINVAL, "bad network arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int32_t noff[2] = {0, n_nodes}, eoff[2] = {0, n_edges};
+    NetIn in{1, noff, eoff, node_xy, src, dst, length_m, lanes, speed_limit_mps};
+    return build_network(c, in);
+}
+
+int32_t lpsim_load_trips(lpsim_ctx *c, int64_t n_trips, const int32_t *depart_step,
+                         const int64_t *route_offsets, const int32_t *route_edges) {
+    if (!c) return LPSIM_EINVAL;
+    if (c->poisoned) return fail(c, LPSIM_EDEVICE, "context poisoned");
+    if (!c->have_net) return fail(c, LPSIM_ESTATE, "load a network first");
+    if (c->n_scen != 1) return fail(c, LPSIM_ESTATE, "context holds a batch; use lpsim_batch_load");
+    if (n_trips < 0 || (n_trips > 0 && (!depart_step || !route_offsets || !route_edges)))
+        return fail(c, LPSIM_EINVAL, "bad trip arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int64_t toff[2] = {0, n_trips};
+    const int64_t zero = 0;
+    TripIn in{toff, depart_step, n_trips ? route_offsets : &zero, route_edges, nullptr};
+    return build_trips(c, in);
+}
+
+int32_t lpsim_batch_load(lpsim_ctx *c, int32_t n_scen, const int32_t *node_off, const int32_t *edge_off,
+                         const int64_t *trip_off, const float *node_xy, const int32_t *src,
+                         const int32_t *dst, const float *length_m, const uint8_t *lanes,
+                         const float *speed_limit_mps, const int32_t *depart_step,
+                         const int64_t *route_offsets, const int32_t *route_edges, const uint64_t *seeds) {
+    if (!c) return LPSIM_EINVAL;
+    if (c->poisoned) return fail(c, LPSIM_EDEVICE, "context poisoned");
+    if (n_scen < 1 || !node_off || !edge_off || !trip_off || !src || !dst || !length_m || !lanes ||
+        !speed_limit_mps || !route_offsets)
+        return fail(c, LPSIM_EINVAL, "bad batch arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    NetIn in{n_scen, node_off, edge_off, node_xy, src, dst, length_m, lanes, speed_limit_mps};
+    int32_t rc = build_network(c, in);
+    if (rc) return rc;
+    TripIn tin{trip_off, depart_step, route_offsets, route_edges, seeds};
+    return build_trips(c, tin);
+}
+
+int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(c, LPSIM_EINVAL, "n_steps < 0");
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->own;
+    c->last = s;
+    if (c->timing || c->graph_steps == 0) {
+        for (int32_t t = 0; t < n_steps; ++t)
+            if ((rc = step_direct(c, s))) return rc;
+    } else {
+        if (!c->g_full && (rc = build_graphs(c))) return rc;
+        int32_t left = n_steps;
+        while (left >= c->graph_steps) {
+            HIPCHK(c, hipGraphLaunch(c->g_full, s));
+            left -= c->graph_steps;
+        }
+        for (; left > 0; --left) HIPCHK(c, hipGraphLaunch(c->g_one, s));
+    }
+    if (!hip_stream) HIPCHK(c, hipStreamSynchronize(s));
+    return LPSIM_OK;
+}
+
+int32_t lpsim_edge_stats(lpsim_ctx *c, int64_t *tt_sum_steps, int32_t *n_exits, int32_t *inflow_bin,
+                         int32_t *exits_bin, int64_t *tt_sum_bin, int64_t *occ_steps_bin) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if ((rc = sync_all(c))) return rc;
+    const size_t E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
+    const Dev &d = c->d;
+    auto perm_rows = [&](auto *dst_ext, const auto &src_int, size_t width) {
+        for (size_t i = 0; i < E; ++i) {
+            const size_t e = (size_t)c->ext_of_int[i];
+            std::memcpy(dst_ext + e * width, src_int.data() + i * width, width * sizeof(src_int[0]));
+        }
+    };
+    if (tt_sum_steps) {
+        std::vector<int64_t> t(E);
+        HIPCHK(c, hipMemcpy(t.data(), d.tt_sum, E * 8, hipMemcpyDeviceToHost));
+        perm_rows(tt_sum_steps, t, 1);
+    }
+    if (n_exits) {
+        std::vector<int32_t> t(E);
+        HIPCHK(c, hipMemcpy(t.data(), d.n_exits, E * 4, hipMemcpyDeviceToHost));
+        perm_rows(n_exits, t, 1);
+    }
+    if (inflow_bin) {
+        std::vector<int32_t> t(E * B);
+        HIPCHK(c, hipMemcpy(t.data(), d.inflow_bin, E * B * 4, hipMemcpyDeviceToHost));
+        perm_rows(inflow_bin, t, B);
+    }
+    if (exits_bin) {
+        std::vector<int32_t> t(E * B);
+        HIPCHK(c, hipMemcpy(t.data(), d.exits_bin, E * B * 4, hipMemcpyDeviceToHost));
+        perm_rows(exits_bin, t, B);
+    }
+    if (tt_sum_bin) {
+        std::vector<int64_t> t(E * B);
+        HIPCHK(c, hipMemcpy(t.data(), d.tt_bin, E * B * 8, hipMemcpyDeviceToHost));
+        perm_rows(tt_sum_bin, t, B);
+    }
+    if (occ_steps_bin) {
+        std::vector<int64_t> t(E * B);
+        HIPCHK(c, hipMemcpy(t.data(), d.occ_bin, E * B * 8, hipMemcpyDeviceToHost));
+        // vehicles still on an edge: the steps they have spent there so far
+        Ctrl ct;
+        if ((rc = read_ctrl(c, ct))) return rc;
+        HostSlots h;
+        if ((rc = read_slots(c, ct, h))) return rc;
+        const int32_t bs = c->dp.bin_steps, nb = c->dp.n_bins;
+        for (size_t i = 0; i < h.m.size(); ++i) {
+            if (h.m[i] & M_DEAD) continue;
+            const int32_t en = h.ent[i], ex = ct.k;
+            if (ex <= en) continue;
+            const int32_t b0 = std::min(en / bs, nb - 1), b1 = std::min((ex - 1) / bs, nb - 1);
+            for (int32_t b = b0; b <= b1; ++b) {
+                const int32_t lo = b * bs, hi = (b == nb - 1) ? 0x7fffffff : lo + bs;
+                t[(size_t)h.e[i] * B + (size_t)b] += std::min(ex, hi) - std::max(en, lo);
+            }
+        }
+        perm_rows(occ_steps_bin, t, B);
+    }
+    return LPSIM_OK;
+}
+
+int32_t lpsim_get_vehicles(lpsim_ctx *c, int32_t *edge, uint8_t *lane, int32_t *cell, float *x, float *v,
+                           int32_t *arrival_step, uint8_t *status) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if ((rc = sync_all(c))) return rc;
+    const size_t N = (size_t)c->n_trips;
+    std::vector<uint8_t> st(N + 1);
+    std::vector<int32_t> arr(N + 1);
+    HIPCHK(c, hipMemcpy(st.data(), c->d.status, N + 1, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(arr.data(), c->d.arrival, (N + 1) * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < N; ++i) {
+        if (edge) edge[i] = -1;
+        if (lane) lane[i] = 0;
+        if (cell) cell[i] = -1;
+        if (x) x[i] = 0.0f;
+        if (v) v[i] = 0.0f;
+        if (arrival_step) arrival_step[i] = arr[i];
+        if (status) status[i] = st[i];
+    }
+    Ctrl ct;
+    if ((rc = read_ctrl(c, ct))) return rc;
+    HostSlots h;
+    if ((rc = read_slots(c, ct, h))) return rc;
+    for (size_t i = 0; i < h.m.size(); ++i) {
+        if (h.m[i] & M_DEAD) continue;
+        const size_t id = h.id[i];
+        if (id >= N) return fail(c, LPSIM_EINVAL, "corrupt slot %zu", i);
+        if (edge) {
+            // global input edge id -> scenario-local id
+            const int32_t g = c->ext_of_int[h.e[i]];
+            const int32_t s = (int32_t)(std::upper_bound(c->edge_off.begin(), c->edge_off.end(), g) -
+                                        c->edge_off.begin()) - 1;
+            edge[id] = g - c->edge_off[s];
+        }
+        if (lane) lane[id] = (uint8_t)(h.m[i] & M_LANE);
+        if (cell) cell[id] = (int32_t)h.x[i];
+        if (x) x[id] = h.x[i];
+        if (v) v[id] = h.v[i];
+    }
+    return LPSIM_OK;
+}
+
+int32_t lpsim_get_counters(lpsim_ctx *c, lpsim_counters *out) {
+    if (!out) return LPSIM_EINVAL;
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if ((rc = sync_all(c))) return rc;
+    std::vector<unsigned long long> part((size_t)MAX_BLOCKS * NPART);
+    HIPCHK(c, hipMemcpy(part.data(), c->d.partial, part.size() * 8, hipMemcpyDeviceToHost));
+    unsigned long long tot[NPART] = {0};
+    for (size_t b = 0; b < (size_t)MAX_BLOCKS; ++b)
+        for (int j = 0; j < NPART; ++j) tot[j] += part[b * NPART + j];
+    Ctrl ct;
+    if ((rc = read_ctrl(c, ct))) return rc;
+    out->step = ct.k;
+    out->active = ct.n_alive;
+    out->departures = (int64_t)tot[P_DEPARTS];
+    out->waiting = c->n_trips - out->departures;
+    out->arrived = (int64_t)tot[P_ARRIVED];
+    out->vehicle_steps = (int64_t)tot[P_VSTEPS];
+    out->transfers = (int64_t)tot[P_TRANSFERS];
+    out->claims_lost = (int64_t)tot[P_LOST];
+    out->lc_attempts = (int64_t)tot[P_LC_TRY];
+    out->lc_accepts = (int64_t)tot[P_LC_OK];
+    out->watchdog = ct.watchdog;
+    out->scan_bytes = (int64_t)tot[P_SCAN];
+    return LPSIM_OK;
+}
+
+int32_t lpsim_block_edge(lpsim_ctx *c, int32_t edge, int32_t on) {
+    int32_t rc = check_ready(c, false);
+    if (rc) return rc;
+    if (c->n_scen != 1) return fail(c, LPSIM_EINVAL, "block_edge takes a single-scenario context");
+    if (edge < 0 || edge >= c->n_edges) return fail(c, LPSIM_EINVAL, "edge out of range");
+    if ((rc = sync_all(c))) return rc;
+    const int32_t i = c->int_of_ext[edge];
+    if (on) c->aux_h[i] |= AUX_BLOCKED;
+    else c->aux_h[i] &= ~AUX_BLOCKED;
+    HIPCHK(c, hipMemcpy(c->d.aux + i, &c->aux_h[i], 4, hipMemcpyHostToDevice));
+    return LPSIM_OK;
+}
+
+int32_t lpsim_set_launch(lpsim_ctx *c, int32_t block_size, int32_t n_blocks, int32_t graph_steps) {
+    if (!c) return LPSIM_EINVAL;
+    if (block_size < 64 || block_size > 1024 || block_size % 64 || n_blocks < 8 || n_blocks > MAX_BLOCKS ||
+        n_blocks % 8 || graph_steps < 0 || graph_steps > 4096)
+        return fail(c, LPSIM_EINVAL, "bad launch shape");
+    if (c->have_trips) {
+        int32_t rc = sync_all(c);
+        if (rc) return rc;
+    }
+    c->threads = block_size;
+    c->blocks = n_blocks;
+    c->graph_steps = graph_steps;
+    drop_graphs(c);
+    return LPSIM_OK;
+}
+
+int32_t lpsim_set_timing(lpsim_ctx *c, int32_t on) {
+    if (!c) return LPSIM_EINVAL;
+    for (const auto &e : c->ev)
+        if (!e) return fail(c, LPSIM_EDEVICE, "timing events unavailable");
+    if (c->have_trips) {
+        int32_t rc = sync_all(c);
+        if (rc) return rc;
+    }
+    c->timing = on != 0;
+    c->ev_used = 0;
+    for (int i = 0; i < N_PHASES; ++i) {
+        c->ms[i] = 0.0;
+        c->launches[i] = 0;
+    }
+    return LPSIM_OK;
+}
+
+int32_t lpsim_kernel_times(lpsim_ctx *c, double *ms_out, int64_t *launches_out, int32_t n_phases) {
+    if (!c || n_phases < 0) return LPSIM_EINVAL;
+    int32_t rc = harvest_events(c);
+    if (rc) return rc;
+    for (int i = 0; i < n_phases && i < N_PHASES; ++i) {
+        if (ms_out) ms_out[i] = c->ms[i];
+        if (launches_out) launches_out[i] = c->launches[i];
+    }
+    return LPSIM_OK;
+}
+
+// snapshot layout: header, ctrl, partial counters, lane map, trip status and
+// arrival, statistics, live slots
+struct SnapHeader {
+    uint64_t magic;
+    uint64_t n_trips, n_edges, map_bytes, n_bins, n_slots;
+};
+
+static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots) {
+    const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
+    return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)MAX_BLOCKS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
+           E * 12 + E * B * 24 + (size_t)n_slots * 32;
+}
+
+int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
+    if (!bytes) return LPSIM_EINVAL;
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if ((rc = sync_all(c))) return rc;
+    Ctrl ct;
+    if ((rc = read_ctrl(c, ct))) return rc;
+    *bytes = snap_size(c, ct.n_slots);
+    return LPSIM_OK;
+}
+
+int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if (!buf) return LPSIM_EINVAL;
+    if ((rc = sync_all(c))) return rc;
+    Ctrl ct;
+    if ((rc = read_ctrl(c, ct))) return rc;
+    if (bytes < snap_size(c, ct.n_slots)) return fail(c, LPSIM_EINVAL, "snapshot buffer too small");
+    const Dev &d = c->d;
+    const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
+    char *p = (char *)buf;
+    SnapHeader h{SNAP_MAGIC, N, E, c->map_bytes, B, ct.n_slots};
+    std::memcpy(p, &h, sizeof h); p += sizeof h;
+    std::memcpy(p, &ct, sizeof ct); p += sizeof ct;
+    auto get = [&](const void *src, size_t n) -> int32_t {
+        HIPCHK(c, hipMemcpy(p, src, n, hipMemcpyDeviceToHost));
+        p += n;
+        return LPSIM_OK;
+    };
+    if ((rc = get(d.partial, (size_t)MAX_BLOCKS * NPART * 8))) return rc;
+    if ((rc = get(d.map, c->map_bytes))) return rc;
+    if ((rc = get(d.status, N + 1))) return rc;
+    if ((rc = get(d.arrival, (N + 1) * 4))) return rc;
+    if ((rc = get(d.n_exits, E * 4))) return rc;
+    if ((rc = get(d.tt_sum, E * 8))) return rc;
+    if ((rc = get(d.inflow_bin, E * B * 4))) return rc;
+    if ((rc = get(d.exits_bin, E * B * 4))) return rc;
+    if ((rc = get(d.tt_bin, E * B * 8))) return rc;
+    if ((rc = get(d.occ_bin, E * B * 8))) return rc;
+    const Slots &S = d.buf[ct.cur];
+    const size_t n = ct.n_slots;
+    if ((rc = get(S.x, n * 4))) return rc;
+    if ((rc = get(S.v, n * 4))) return rc;
+    if ((rc = get(S.e, n * 4))) return rc;
+    if ((rc = get(S.m, n * 4))) return rc;
+    if ((rc = get(S.id, n * 4))) return rc;
+    if ((rc = get(S.rp, n * 4))) return rc;
+    if ((rc = get(S.rend, n * 4))) return rc;
+    if ((rc = get(S.ent, n * 4))) return rc;
+    return LPSIM_OK;
+}
+
+int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if (!buf || bytes < sizeof(SnapHeader) + sizeof(Ctrl)) return fail(c, LPSIM_EINVAL, "snapshot too small");
+    if ((rc = sync_all(c))) return rc;
+    const char *p = (const char *)buf;
+    SnapHeader h;
+    std::memcpy(&h, p, sizeof h); p += sizeof h;
+    const Dev &d = c->d;
+    const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
+    if (h.magic != SNAP_MAGIC || h.n_trips != N || h.n_edges != E || h.map_bytes != c->map_bytes || h.n_bins != B ||
+        h.n_slots > c->slot_cap || bytes < snap_size(c, h.n_slots))
+        return fail(c, LPSIM_EINVAL, "snapshot does not match this instance");
+    Ctrl ct;
+    std::memcpy(&ct, p, sizeof ct); p += sizeof ct;
+    ct.cur = 0;
+    auto put = [&](void *dst, size_t n) -> int32_t {
+        HIPCHK(c, hipMemcpy(dst, p, n, hipMemcpyHostToDevice));
+        p += n;
+        return LPSIM_OK;
+    };
+    if ((rc = put(d.partial, (size_t)MAX_BLOCKS * NPART * 8))) return rc;
+    if ((rc = put(d.map, c->map_bytes))) return rc;
+    if ((rc = put(d.status, N + 1))) return rc;
+    if ((rc = put(d.arrival, (N + 1) * 4))) return rc;
+    if ((rc = put(d.n_exits, E * 4))) return rc;
+    if ((rc = put(d.tt_sum, E * 8))) return rc;
+    if ((rc = put(d.inflow_bin, E * B * 4))) return rc;
+    if ((rc = put(d.exits_bin, E * B * 4))) return rc;
+    if ((rc = put(d.tt_bin, E * B * 8))) return rc;
+    if ((rc = put(d.occ_bin, E * B * 8))) return rc;
+    const Slots &S = d.buf[0];
+    const size_t n = h.n_slots;
+    if ((rc = put(S.x, n * 4))) return rc;
+    if ((rc = put(S.v, n * 4))) return rc;
+    if ((rc = put(S.e, n * 4))) return rc;
+    if ((rc = put(S.m, n * 4))) return rc;
+    if ((rc = put(S.id, n * 4))) return rc;
+    if ((rc = put(S.rp, n * 4))) return rc;
+    if ((rc = put(S.rend, n * 4))) return rc;
+    if ((rc = put(S.ent, n * 4))) return rc;
+    HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
+    HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
+    HIPCHK(c, hipDeviceSynchronize());
+    return LPSIM_OK;
+}
+
+int32_t lpsim_query(const lpsim_ctx *c, int32_t which) {
+    if (!c) return LPSIM_EINVAL;
+    if (which == 0) return c->dp.W;
+    if (which == 1) return c->look.empty() ? LPSIM_ESTATE : c->look[0];
+    if (which == 2) return c->dp.bin_steps;
+    return LPSIM_EINVAL;
+}
+
+const char *lpsim_last_error(const lpsim_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"
