@@ -212,7 +212,8 @@ int32_t lpsim_set_launch(lpsim_ctx *ctx, int32_t block_size, int32_t n_blocks,
 /* Kernel timing for measurement: when on, lpsim_step launches kernels one by
  * one and records a HIP event pair around each on the work stream;
  * lpsim_kernel_times then returns the summed milliseconds and launch counts
- * of the phases (0 move, 1 resolve, 2 lane change, 3 commit, 4 compact).
+ * of the phases (0 move, 1 departure requests, 2 resolve, 3 departures,
+ * 4 lane change, 5 commit and end of step, 6 reorder).
  * Turning it on or off resets the sums. */
 int32_t lpsim_set_timing(lpsim_ctx *ctx, int32_t on);
 int32_t lpsim_kernel_times(lpsim_ctx *ctx, double *ms_out, int64_t *launches_out,

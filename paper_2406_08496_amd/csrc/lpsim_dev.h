@@ -12,12 +12,14 @@ constexpr uint8_t FREE_BYTE = 255;  // lane-map byte of an empty cell
 // trip status
 constexpr uint8_t ST_WAIT = 0, ST_ACTIVE = 1, ST_DONE = 2;
 
-// slot meta word: lane | flags | step kind | old lane | old cell
+// slot meta word: lane | flags | step kind | old lane | required lane | old cell
 constexpr uint32_t M_LANE = 7u;             // bits 0-2
 constexpr uint32_t M_DEAD = 1u << 3;        // slot no longer holds a vehicle
 constexpr uint32_t M_ENTERED = 1u << 4;     // entered its edge in this step
 constexpr uint32_t M_KIND_SHIFT = 6;        // bits 6-7: K_MOVE / K_ARRIVE / K_CLAIM
 constexpr uint32_t M_OLDLANE_SHIFT = 8;     // bits 8-10 (accepted lane change)
+constexpr uint32_t M_REQ_SHIFT = 11;        // bits 11-13: lane required for the next edge
+constexpr uint32_t M_REQ = 7u << M_REQ_SHIFT;
 constexpr uint32_t M_CELL_SHIFT = 16;       // bits 16-31: cell at step start
 constexpr uint32_t K_MOVE = 0, K_ARRIVE = 1, K_CLAIM = 2;
 
@@ -51,19 +53,18 @@ struct Ctrl {
     uint32_t cur;          // which slot buffer is live
     uint32_t n_slots;      // slots in use in the live buffer (some may be dead)
     uint32_t n_new;        // departures appended this step (above n_slots)
-    uint32_t n_lc;         // accepted lane changes this step
-    uint32_t n_comp;       // compaction output count
-    uint32_t wait_lo;      // first departure-order position that may still wait
-    uint32_t wait_lo_next;
-    uint32_t arr_step;     // arrivals this step
-    uint32_t events;       // any entry or exit this step
-    uint32_t done_commit;  // last-block counters
-    uint32_t done_compact;
+    uint32_t n_comp;       // live slots counted by the reorder
+    uint32_t wq_cur;       // which waiting-queue buffer is live
+    uint32_t n_wq;         // due trips still waiting (live queue)
+    uint32_t n_wq_next;    // queue being built this step
+    uint32_t dep_ev;       // a trip departed this step
+    uint32_t dep_done;     // departure-order positions already due
 };
 
 struct Slots {
     float *x, *v;
     int32_t *e;     // internal edge id
+    int32_t *en;    // next edge on the route (internal id), -1 on the last edge
     uint32_t *m;    // meta word
     uint32_t *id;   // trip id (global)
     uint32_t *rp;   // absolute route index of the current edge
@@ -77,7 +78,17 @@ struct Dev {
     Slots buf[2];
     uint32_t *scl;  // claim word of a crossing vehicle (this step)
     float *sxo;     // its position before the move
-    uint32_t *lc_list;
+    // per-step work lists, one segment per block: block b of the vehicle
+    // kernels owns entries [lo_b, lo_b + count[b]) where [lo_b, hi_b) is its
+    // share of the step's work items (so no global counter is contended)
+    uint4 *rl_list;     // vehicles with an entry request, an arrival or a changed map
+                        // byte: {slot, lane-map offset of its lane, old | new cell << 16,
+                        // new speed byte | step kind << 8}
+    uint32_t *lcc_list; // slots that may change lane
+    uint32_t *lc_list;  // accepted lane changes
+    uint32_t *rl_cnt, *lcc_cnt, *lc_cnt;  // [MAX_BLOCKS]
+    uint32_t *blk_arr;  // [MAX_BLOCKS] arrivals of the block this step
+    uint32_t *blk_ev;   // [MAX_BLOCKS] any entry or exit in the block this step
     const uint4 *edge;
     uint32_t *aux;
     const int32_t *escen;
@@ -94,6 +105,15 @@ struct Dev {
     uint8_t *status;
     int32_t *arrival;
     uint8_t *dclaim;
+    uint32_t *wq[2];      // due trips that have not entered yet
+    const uint4 *orig;    // per trip: claim word, lane-map offset of the start
+                          // lane, first edge, route index of the first edge
+    // per-edge counting sort of the slots (locality), every few steps
+    int32_t n_edges;
+    uint32_t *ecnt;       // [n_edges] vehicles per edge, zero between sorts
+    uint32_t *eoff;       // [n_edges] offset inside the edge's 4096-edge chunk
+    uint32_t *csum;       // [chunks] chunk offsets
+    uint32_t *srank;      // [slot] rank inside its edge
     int32_t *n_exits;
     unsigned long long *tt_sum;
     int32_t *inflow_bin, *exits_bin;
@@ -102,9 +122,14 @@ struct Dev {
 };
 
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s);
+void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s);
+void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s);
+constexpr int CAND_BLOCKS = 128;    // grid of the departure kernels (1024 threads)
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s);
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s);
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_compact(const Dev &d, int blocks, int threads, hipStream_t s);
+void launch_end(const Dev &d, int blocks, hipStream_t s);
+void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s);
+constexpr int SORT_CHUNK = 4096;  // edges per scan block
 
 }  // namespace lpsim

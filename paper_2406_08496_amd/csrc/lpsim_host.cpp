@@ -19,7 +19,7 @@ using namespace lpsim;
 
 namespace {
 
-constexpr int N_PHASES = 5;
+constexpr int N_PHASES = 7;
 constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
 
 }  // namespace
@@ -61,10 +61,9 @@ struct lpsim_ctx {
     // launch shape
     int threads = 256;
     int blocks = 2048;
-    int commit_blocks = 32;
     int graph_steps = 32;
     hipGraphExec_t g_full = nullptr, g_one = nullptr;
-    int direct_since_compact = 0;
+    int direct_since_reorder = 0;
 
     // timing
     bool timing = false;
@@ -326,6 +325,12 @@ static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
     if ((rc = alloc_n(c, d.tt_bin, nb, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.occ_bin, nb, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.partial, (size_t)MAX_BLOCKS * NPART, c->net_allocs))) return rc;
+    const size_t n_chunks = ((size_t)E + SORT_CHUNK - 1) / SORT_CHUNK;
+    if ((rc = alloc_n(c, d.ecnt, (size_t)E, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.eoff, (size_t)E, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.csum, n_chunks + 1, c->net_allocs))) return rc;
+    HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)E * 4));
+    d.n_edges = E;
     if ((rc = alloc_n(c, d.ctrl, 1, c->net_allocs))) return rc;
     HIPCHK(c, hipMemset(d.map, 0xff, off + 256));
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)slot * 4));
@@ -357,8 +362,10 @@ static int32_t reset_run_state(lpsim_ctx *c) {
     HIPCHK(c, hipMemset(d.status, 0, N + 1));
     HIPCHK(c, hipMemset(d.arrival, 0xff, (N + 1) * 4));
     HIPCHK(c, hipMemset(d.dclaim, 0, N + 1));
+    HIPCHK(c, hipMemset(d.ecnt, 0, E * 4));
+    for (uint32_t *a : {d.rl_cnt, d.lcc_cnt, d.lc_cnt, d.blk_arr, d.blk_ev})
+        HIPCHK(c, hipMemset(a, 0, (size_t)MAX_BLOCKS * 4));
     Ctrl ct{};
-    ct.wait_lo_next = 0xffffffffu;
     HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
     // the blocked flags survive a reload of trips
     HIPCHK(c, hipMemcpy(d.aux, c->aux_h.data(), c->aux_h.size() * 4, hipMemcpyHostToDevice));
@@ -432,6 +439,23 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     }
     std::vector<uint32_t> dep_hi((size_t)maxdep + 2, (uint32_t)N);  // one spare entry
     for (int32_t k = 0; k <= maxdep; ++k) dep_hi[(size_t)k] = cnt[(size_t)k + 1];
+    // per-trip origin: claim word, lane-map offset of the start lane, first
+    // edge, route index of the first edge (start lane = scenario-local id mod lanes)
+    std::vector<uint4> orig((size_t)std::max<int64_t>(N, 1));
+    {
+        std::vector<uint4> rec_h(c->n_edges);
+        HIPCHK(c, hipMemcpy(rec_h.data(), c->d.edge, (size_t)c->n_edges * 16, hipMemcpyDeviceToHost));
+        for (int32_t s = 0; s < S; ++s) {
+            for (int64_t t = in.trip_off[s]; t < in.trip_off[s + 1]; ++t) {
+                const uint32_t r0 = roff[(size_t)t];
+                const uint32_t e0 = route[r0];
+                const uint4 R = rec_h[e0];
+                const uint32_t C = R.y & 0xffffu, nl = (R.y >> 16) & 0xffu;
+                const uint32_t l0 = (uint32_t)(t - in.trip_off[s]) % nl;
+                orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, r0);
+            }
+        }
+    }
     std::vector<uint64_t> seeds(S);
     std::vector<uint32_t> tbase(S);
     for (int32_t s = 0; s < S; ++s) {
@@ -453,6 +477,9 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if ((rc = upload(c, *(uint32_t **)&order_d, order.data(), order.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint32_t **)&dephi_d, dep_hi.data(), dep_hi.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint64_t **)&seeds_d, seeds.data(), seeds.size(), c->trip_allocs))) return rc;
+    const uint4 *orig_d;
+    if ((rc = upload(c, *(uint4 **)&orig_d, orig.data(), orig.size(), c->trip_allocs))) return rc;
+    d.orig = orig_d;
     if ((rc = upload(c, *(uint32_t **)&tbase_d, tbase.data(), tbase.size(), c->trip_allocs))) return rc;
     d.route = route_d;
     d.route_off = roff_d;
@@ -470,6 +497,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         if ((rc = alloc_n(c, s.x, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.v, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.e, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.en, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.m, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.id, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.rp, cap, c->trip_allocs))) return rc;
@@ -479,9 +507,19 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if ((rc = alloc_n(c, d.scl, cap, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.sxo, cap, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.lc_list, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.rl_list, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lcc_list, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.rl_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lcc_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lc_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.blk_arr, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.blk_ev, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.wq[0], cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.wq[1], cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.srank, cap, c->trip_allocs))) return rc;
     if ((rc = reset_run_state(c))) return rc;
     c->have_trips = true;
-    c->direct_since_compact = 0;
+    c->direct_since_reorder = 0;
     return LPSIM_OK;
 }
 
@@ -490,9 +528,11 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
 
 static void enqueue_step(lpsim_ctx *c, hipStream_t s) {
     launch_move(c->d, c->blocks, c->threads, s);
+    launch_cand(c->d, c->blocks, c->threads, s);
     launch_resolve(c->d, c->blocks, c->threads, s);
+    launch_depart(c->d, c->blocks, c->threads, s);
     if (c->dp.lane_change) launch_lanechg(c->d, c->blocks, c->threads, s);
-    launch_commit(c->d, c->commit_blocks, c->threads, s);
+    launch_commit(c->d, c->blocks, c->threads, s);
 }
 
 static int32_t build_graphs(lpsim_ctx *c) {
@@ -502,7 +542,7 @@ static int32_t build_graphs(lpsim_ctx *c) {
         HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
         const int n = which == 0 ? c->graph_steps : 1;
         for (int t = 0; t < n; ++t) enqueue_step(c, c->own);
-        if (which == 0) launch_compact(c->d, c->blocks, c->threads, c->own);
+        if (which == 0) launch_reorder(c->d, c->blocks, c->threads, c->own);
         HIPCHK(c, hipStreamEndCapture(c->own, &g));
         hipGraphExec_t ex = nullptr;
         HIPCHK(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -543,19 +583,21 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     int32_t rc;
     if (c->timing) {
         if ((rc = timed(c, 0, s, launch_move, c->blocks))) return rc;
-        if ((rc = timed(c, 1, s, launch_resolve, c->blocks))) return rc;
-        if (c->dp.lane_change && (rc = timed(c, 2, s, launch_lanechg, c->blocks))) return rc;
-        if ((rc = timed(c, 3, s, launch_commit, c->commit_blocks))) return rc;
+        if ((rc = timed(c, 1, s, launch_cand, c->blocks))) return rc;
+        if ((rc = timed(c, 2, s, launch_resolve, c->blocks))) return rc;
+        if ((rc = timed(c, 3, s, launch_depart, c->blocks))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, 4, s, launch_lanechg, c->blocks))) return rc;
+        if ((rc = timed(c, 5, s, launch_commit, c->blocks))) return rc;
     } else {
         enqueue_step(c, s);
     }
-    if (++c->direct_since_compact >= std::max(c->graph_steps, 32)) {
+    if (++c->direct_since_reorder >= std::max(c->graph_steps, 32)) {
         if (c->timing) {
-            if ((rc = timed(c, 4, s, launch_compact, c->blocks))) return rc;
+            if ((rc = timed(c, 6, s, launch_reorder, c->blocks))) return rc;
         } else {
-            launch_compact(c->d, c->blocks, c->threads, s);
+            launch_reorder(c->d, c->blocks, c->threads, s);
         }
-        c->direct_since_compact = 0;
+        c->direct_since_reorder = 0;
     }
     HIPCHK(c, hipGetLastError());
     return LPSIM_OK;
@@ -936,13 +978,13 @@ int32_t lpsim_kernel_times(lpsim_ctx *c, double *ms_out, int64_t *launches_out, 
 // arrival, statistics, live slots
 struct SnapHeader {
     uint64_t magic;
-    uint64_t n_trips, n_edges, map_bytes, n_bins, n_slots;
+    uint64_t n_trips, n_edges, map_bytes, n_bins, n_slots, n_wq;
 };
 
-static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots) {
+static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_wq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)MAX_BLOCKS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
-           E * 12 + E * B * 24 + (size_t)n_slots * 32;
+           E * 12 + E * B * 24 + (size_t)n_slots * 36 + (size_t)n_wq * 4;
 }
 
 int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
@@ -952,7 +994,7 @@ int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
     if ((rc = sync_all(c))) return rc;
     Ctrl ct;
     if ((rc = read_ctrl(c, ct))) return rc;
-    *bytes = snap_size(c, ct.n_slots);
+    *bytes = snap_size(c, ct.n_slots, ct.n_wq);
     return LPSIM_OK;
 }
 
@@ -963,11 +1005,11 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = sync_all(c))) return rc;
     Ctrl ct;
     if ((rc = read_ctrl(c, ct))) return rc;
-    if (bytes < snap_size(c, ct.n_slots)) return fail(c, LPSIM_EINVAL, "snapshot buffer too small");
+    if (bytes < snap_size(c, ct.n_slots, ct.n_wq)) return fail(c, LPSIM_EINVAL, "snapshot buffer too small");
     const Dev &d = c->d;
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     char *p = (char *)buf;
-    SnapHeader h{SNAP_MAGIC, N, E, c->map_bytes, B, ct.n_slots};
+    SnapHeader h{SNAP_MAGIC, N, E, c->map_bytes, B, ct.n_slots, ct.n_wq};
     std::memcpy(p, &h, sizeof h); p += sizeof h;
     std::memcpy(p, &ct, sizeof ct); p += sizeof ct;
     auto get = [&](const void *src, size_t n) -> int32_t {
@@ -990,11 +1032,13 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = get(S.x, n * 4))) return rc;
     if ((rc = get(S.v, n * 4))) return rc;
     if ((rc = get(S.e, n * 4))) return rc;
+    if ((rc = get(S.en, n * 4))) return rc;
     if ((rc = get(S.m, n * 4))) return rc;
     if ((rc = get(S.id, n * 4))) return rc;
     if ((rc = get(S.rp, n * 4))) return rc;
     if ((rc = get(S.rend, n * 4))) return rc;
     if ((rc = get(S.ent, n * 4))) return rc;
+    if ((rc = get(d.wq[ct.wq_cur], (size_t)ct.n_wq * 4))) return rc;
     return LPSIM_OK;
 }
 
@@ -1009,11 +1053,12 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     const Dev &d = c->d;
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     if (h.magic != SNAP_MAGIC || h.n_trips != N || h.n_edges != E || h.map_bytes != c->map_bytes || h.n_bins != B ||
-        h.n_slots > c->slot_cap || bytes < snap_size(c, h.n_slots))
+        h.n_slots > c->slot_cap || h.n_wq > c->slot_cap || bytes < snap_size(c, h.n_slots, h.n_wq))
         return fail(c, LPSIM_EINVAL, "snapshot does not match this instance");
     Ctrl ct;
     std::memcpy(&ct, p, sizeof ct); p += sizeof ct;
     ct.cur = 0;
+    ct.wq_cur = 0;
     auto put = [&](void *dst, size_t n) -> int32_t {
         HIPCHK(c, hipMemcpy(dst, p, n, hipMemcpyHostToDevice));
         p += n;
@@ -1034,12 +1079,15 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(S.x, n * 4))) return rc;
     if ((rc = put(S.v, n * 4))) return rc;
     if ((rc = put(S.e, n * 4))) return rc;
+    if ((rc = put(S.en, n * 4))) return rc;
     if ((rc = put(S.m, n * 4))) return rc;
     if ((rc = put(S.id, n * 4))) return rc;
     if ((rc = put(S.rp, n * 4))) return rc;
     if ((rc = put(S.rend, n * 4))) return rc;
     if ((rc = put(S.ent, n * 4))) return rc;
+    if ((rc = put(d.wq[0], (size_t)h.n_wq * 4))) return rc;
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
+    HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
     HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
     HIPCHK(c, hipDeviceSynchronize());
     return LPSIM_OK;

@@ -6,21 +6,26 @@
 //
 //   move     reads the lane map of step k: leader scan, IDM / free move,
 //            stop line, crossing; entry requests of crossing vehicles and of
-//            departing trips go into one 32-bit word per target lane by
-//            atomicMin of the trip id (exclusive entry, lowest id wins);
+//            due trips go into one 32-bit word per target lane by atomicMin
+//            of the trip id (exclusive entry, lowest id wins);
 //   resolve  winners enter, losers wait at the last cell, arrivals leave;
 //            each vehicle clears its old cell byte and writes its new one --
 //            no two vehicles touch the same byte in this kernel (a mover never
 //            lands on a cell another vehicle occupied at step k, entries need
-//            the first W cells free); per-edge statistics by atomics;
+//            the first W cells free); per-edge statistics by atomics; trips
+//            that could not enter go to the next waiting queue;
 //   lanechg  mandatory lane change decided on the post-move map;
 //   commit   writes the accepted lane changes into the map, then the last
 //            block to finish does the step's bookkeeping (clock, counts).
-//   compact  (every few steps) moves live vehicle slots together.
+//   reorder  (every few steps) a counting sort of the live vehicle slots by
+//            edge: drops finished vehicles and puts vehicles of one edge next
+//            to each other, so neighbouring lanes share cache lines.
 //
 // Vehicle state lives in slots (structure of arrays) that only hold vehicles
 // on the road; the per-step control words live in device memory so that a
-// captured HIP graph of many steps replays without host involvement.
+// captured HIP graph of many steps replays without host involvement.  Every
+// loop walks whole wavefronts (64 lanes) together so that list appends can be
+// aggregated per wavefront with a ballot.
 //
 // All floating point is binary32 with no contraction (-ffp-contract=off) and
 // IEEE division, in exactly the order of the method's definition, so results
@@ -49,6 +54,20 @@ __device__ __forceinline__ void block_range(uint64_t total, uint64_t &lo, uint64
     if (lo > total) lo = total;
 }
 
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+// wavefront-aggregated append: returns this lane's index in `list` (valid if pred)
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
+    const uint64_t mask = __ballot(pred);
+    uint32_t base = 0;
+    if (mask) {
+        const uint32_t leader = (uint32_t)__ffsll((long long)mask) - 1u;
+        if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+        base = __shfl(base, (int)leader);
+    }
+    return base + (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
 __device__ __forceinline__ uint8_t speed_byte(float v) {
     float c = v < 254.0f ? v : 254.0f;
     return (uint8_t)(int32_t)c;
@@ -59,28 +78,85 @@ __device__ __forceinline__ int32_t bin_of(const Params &p, int32_t step) {
     return b < p.n_bins - 1 ? b : p.n_bins - 1;
 }
 
-// first occupied cell in [lo, hi] of one lane, or -1
-__device__ __forceinline__ int32_t first_occ(const uint8_t *lane, int32_t lo, int32_t hi) {
-    for (int32_t c = lo; c <= hi; ++c)
-        if (lane[c] != FREE_BYTE) return c;
+// ---------------------------------------------------------------------------
+// lane-map scans with aligned 16-byte loads (the map has 256 spare bytes at
+// its end and starts 256-aligned, so whole chunks are always readable)
+
+__device__ __forceinline__ uint4 ld16(const uint8_t *map, uint32_t a) {
+    return *reinterpret_cast<const uint4 *>(map + a);
+}
+
+// bit mask of the occupied bytes (8 bits per byte) of an 8-byte word that lie
+// inside [s, e]; `base` is the map offset of the word's first byte
+__device__ __forceinline__ uint64_t occ_bits(uint64_t w, uint32_t base, uint32_t s, uint32_t e) {
+    uint64_t t = ~w;  // nonzero byte <=> byte != 0xFF
+    if (base < s) {
+        const uint32_t d = s - base;
+        t = d >= 8 ? 0ull : (t & (~0ull << (8 * d)));
+    }
+    if (base + 7 > e) {
+        const int32_t nb = (int32_t)e - (int32_t)base + 1;
+        t = nb <= 0 ? 0ull : (t & ((1ull << (8 * nb)) - 1ull));
+    }
+    return t;
+}
+
+// first occupied cell in [lo, hi] of the lane starting at map offset `lane`, or -1
+__device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi) {
+    if (lo > hi) return -1;
+    const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
+    for (uint32_t a = s & ~15u; a <= e; a += 64) {
+        const uint32_t nch = min(4u, ((e - a) >> 4) + 1u);
+        uint4 c0 = ld16(map, a), c1, c2, c3;
+        if (nch > 1) c1 = ld16(map, a + 16);
+        if (nch > 2) c2 = ld16(map, a + 32);
+        if (nch > 3) c3 = ld16(map, a + 48);
+        for (uint32_t j = 0; j < nch; ++j) {
+            const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
+            const uint32_t b = a + 16 * j;
+            uint64_t t = occ_bits((uint64_t)c.x | ((uint64_t)c.y << 32), b, s, e);
+            if (t) return (int32_t)(b + ((uint32_t)__builtin_ctzll(t) >> 3) - lane);
+            t = occ_bits((uint64_t)c.z | ((uint64_t)c.w << 32), b + 8, s, e);
+            if (t) return (int32_t)(b + 8 + ((uint32_t)__builtin_ctzll(t) >> 3) - lane);
+        }
+    }
     return -1;
 }
 
-// first occupied cell going down from hi to lo, or -1
-__device__ __forceinline__ int32_t last_occ(const uint8_t *lane, int32_t hi, int32_t lo) {
-    for (int32_t c = hi; c >= lo; --c)
-        if (lane[c] != FREE_BYTE) return c;
+// highest occupied cell in [lo, hi], or -1
+__device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi) {
+    if (lo > hi) return -1;
+    const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
+    const uint32_t first = s & ~15u;
+    for (int64_t a = (int64_t)(e & ~15u); a >= (int64_t)first; a -= 64) {
+        const uint32_t nch = min(4u, (uint32_t)((a - (int64_t)first) >> 4) + 1u);
+        uint4 c0 = ld16(map, (uint32_t)a), c1, c2, c3;
+        if (nch > 1) c1 = ld16(map, (uint32_t)a - 16);
+        if (nch > 2) c2 = ld16(map, (uint32_t)a - 32);
+        if (nch > 3) c3 = ld16(map, (uint32_t)a - 48);
+        for (uint32_t j = 0; j < nch; ++j) {
+            const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
+            const uint32_t b = (uint32_t)a - 16 * j;
+            uint64_t t = occ_bits((uint64_t)c.z | ((uint64_t)c.w << 32), b + 8, s, e);
+            if (t) return (int32_t)(b + 8 + ((63u - (uint32_t)__builtin_clzll(t)) >> 3) - lane);
+            t = occ_bits((uint64_t)c.x | ((uint64_t)c.y << 32), b, s, e);
+            if (t) return (int32_t)(b + ((63u - (uint32_t)__builtin_clzll(t)) >> 3) - lane);
+        }
+    }
     return -1;
 }
 
-__device__ __forceinline__ bool entry_free(const Dev &d, const uint4 &E, int32_t e, int32_t l) {
+__device__ __forceinline__ uint32_t lane_base(const uint4 &E, uint32_t l) {
+    return E.x + l * (uint32_t)E_CELLS(E);
+}
+
+__device__ __forceinline__ bool entry_free(const Dev &d, const uint4 &E, int32_t e, uint32_t l) {
     if (d.aux[e] & AUX_BLOCKED) return false;
-    const int32_t C = E_CELLS(E);
-    const uint8_t *lp = d.map + E.x + (uint32_t)l * (uint32_t)C;
-    for (int32_t c = 0; c < d.p.W; ++c)
-        if (lp[c] != FREE_BYTE) return false;
-    return true;
+    return first_occ(d.map, lane_base(E, l), 0, d.p.W - 1) < 0;
 }
+
+// ---------------------------------------------------------------------------
+// car following
 
 __device__ __forceinline__ void idm_follow(const Params &p, float x, float v, float v0, float gap,
                                            float vl, float &xn, float &vn) {
@@ -125,6 +201,9 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
     return z ^ (z >> 31);
 }
+
+// ---------------------------------------------------------------------------
+// statistics
 
 __device__ __forceinline__ void add_exit(const Dev &d, int32_t e, int32_t enter, int32_t ex) {
     const int32_t tt = ex - enter;
@@ -171,120 +250,187 @@ __device__ __forceinline__ void counts_flush(const Dev &d, BlockCounts *s) {
     }
 }
 
+// the trip at position q of this step's departure candidates: the live
+// waiting queue first, then the trips that fall due at this step
+__device__ __forceinline__ uint32_t candidate(const Dev &d, const Ctrl *ctl, uint32_t q) {
+    const uint32_t nwq = ctl->n_wq;
+    return q < nwq ? d.wq[ctl->wq_cur][q] : d.dep_order[ctl->dep_done + (q - nwq)];
+}
+
+// exclusive scan of 1024 values, one per thread (16 wavefronts)
+__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int dlt = 1; dlt < 64; dlt <<= 1) {
+        const uint32_t t = __shfl_up(x, dlt);
+        if (lane >= (uint32_t)dlt) x += t;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        uint32_t y = wsum[threadIdx.x];
+        for (int dlt = 1; dlt < 16; dlt <<= 1) {
+            const uint32_t t = __shfl_up(y, dlt);
+            if (threadIdx.x >= (uint32_t)dlt) y += t;
+        }
+        wsum[16 + threadIdx.x] = y;
+    }
+    __syncthreads();
+    total = wsum[31];
+    const uint32_t before = w ? wsum[16 + w - 1] : 0u;
+    return before + x - v;
+}
+
+// lane required to leave toward edge `en`: the node's out-edges split the
+// lanes of the incoming edge in proportion to their rank
+__device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int32_t lanes_e) {
+    const uint32_t ax = d.aux[en];
+    return (uint32_t)(((int32_t)(ax & 0xffu) * lanes_e) / (int32_t)((ax >> 8) & 0xffu));
+}
+
 // ---------------------------------------------------------------------------
 // move: longitudinal intent from step-k state
 
 __global__ __launch_bounds__(1024) void k_move(Dev d) {
     __shared__ BlockCounts cnt;
+    __shared__ uint32_t s_rl, s_lcc;
+    if (threadIdx.x == 0) {
+        s_rl = 0;
+        s_lcc = 0;
+    }
     counts_init(&cnt);
     const Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
-    const uint32_t wlo = ctl->wait_lo;
-    const uint32_t dhi = dep_hi_of(d, k);
-    const uint32_t ncand = dhi > wlo ? dhi - wlo : 0;
-    const Slots S = d.buf[ctl->cur];
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
-    uint64_t lo, hi;
-    block_range((uint64_t)n + ncand, lo, hi);
+    uint64_t lo64, hi64;
+    block_range(n, lo64, hi64);
+    const uint32_t vlo = (uint32_t)lo64, nv = (uint32_t)(hi64 - lo64);
     unsigned int alive = 0, scanned = 0;
-    for (uint64_t it = lo + threadIdx.x; it < hi; it += blockDim.x) {
-        if (it < n) {
-            const uint32_t i = (uint32_t)it;
+    for (uint32_t base = 0; base < nv; base += blockDim.x) {
+        const uint32_t it = base + threadIdx.x;
+        const uint32_t i = vlo + it;
+        bool need_resolve = false, lc_cand = false;
+        uint4 rl = make_uint4(0, 0, 0, 0);
+        if (it < nv) {
             const uint32_t m = S.m[i];
-            if (m & M_DEAD) continue;
-            ++alive;
-            const float x = S.x[i], v = S.v[i];
-            const int32_t e = S.e[i];
-            const uint32_t lane = m & M_LANE;
-            const uint4 E = d.edge[e];
-            const int32_t C = E_CELLS(E), D = E_LOOK(E);
-            const float v0 = __uint_as_float(E.z);
-            const uint8_t *lp = d.map + E.x + lane * (uint32_t)C;
-            const int32_t c = (int32_t)x;
-            const int32_t top = c + D < C - 1 ? c + D : C - 1;
-            const int32_t cl = first_occ(lp, c + 1, top);
-            float x2, v2;
-            uint32_t rp = 0, re = 0;
-            bool have_route = false;
-            scanned += (uint32_t)((cl >= 0 ? cl : top) - c);
-            if (cl >= 0) {
-                const float vl = (float)lp[cl];
-                const float gap = ((float)cl - x) - p.L;
-                idm_follow(p, x, v, v0, gap, vl, x2, v2);
-                const float lim = (float)cl - p.L;
-                if (x2 > lim) {
-                    x2 = x > lim ? x : lim;
-                    v2 = v2 < vl ? v2 : vl;
+            if (!(m & M_DEAD)) {
+                ++alive;
+                const float x = S.x[i], v = S.v[i];
+                const int32_t e = S.e[i], en = S.en[i];
+                const uint32_t lane = m & M_LANE;
+                const uint4 E = d.edge[e];
+                const int32_t C = E_CELLS(E), D = E_LOOK(E);
+                const float v0 = __uint_as_float(E.z);
+                const uint32_t lb = lane_base(E, lane);
+                const int32_t c = (int32_t)x;
+                // stop line inside the look-ahead: the next edge's entry matters
+                const bool near = en >= 0 && c + D >= C;
+                uint4 En = make_uint4(0, 0, 0, 0);
+                uint32_t ax_en = 0;
+                if (near) {
+                    En = d.edge[en];
+                    ax_en = d.aux[en];
                 }
-            } else {
-                bool stop = false;
-                if (c + D >= C) {
-                    rp = S.rp[i];
-                    re = S.rend[i];
-                    have_route = true;
-                    if (rp + 1 < re) {
-                        const int32_t en = (int32_t)d.route[rp + 1];
-                        const uint4 En = d.edge[en];
-                        const int32_t nle = E_LANES(En);
-                        const int32_t ln = (int32_t)lane < nle - 1 ? (int32_t)lane : nle - 1;
-                        stop = !entry_free(d, En, en, ln);
-                        // route position (8), next edge record (16) and flags (4), entry window
-                        scanned += 28u + (uint32_t)p.W;
-                    }
-                }
-                if (stop) {
-                    const float gap = (float)C - x;
-                    idm_follow(p, x, v, v0, gap, 0.0f, x2, v2);
-                    const float lim = (float)(C - 1);
+                const int32_t top = c + D < C - 1 ? c + D : C - 1;
+                const int32_t cl = first_occ(d.map, lb, c + 1, top);
+                scanned += (uint32_t)((cl >= 0 ? cl : top) - c);
+                float x2, v2;
+                if (cl >= 0) {
+                    const float vl = (float)d.map[lb + (uint32_t)cl];
+                    const float gap = ((float)cl - x) - p.L;
+                    idm_follow(p, x, v, v0, gap, vl, x2, v2);
+                    const float lim = (float)cl - p.L;
                     if (x2 > lim) {
                         x2 = x > lim ? x : lim;
-                        v2 = 0.0f;
+                        v2 = v2 < vl ? v2 : vl;
                     }
                 } else {
-                    free_move(p, x, v, v0, x2, v2);
+                    bool stop = false;
+                    if (near) {
+                        const uint32_t nle = (uint32_t)E_LANES(En);
+                        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
+                        stop = (ax_en & AUX_BLOCKED) || first_occ(d.map, lane_base(En, ln), 0, p.W - 1) >= 0;
+                        // next edge record (16), its flags (4), entry window
+                        scanned += 20u + (uint32_t)p.W;
+                    }
+                    if (stop) {
+                        const float gap = (float)C - x;
+                        idm_follow(p, x, v, v0, gap, 0.0f, x2, v2);
+                        const float lim = (float)(C - 1);
+                        if (x2 > lim) {
+                            x2 = x > lim ? x : lim;
+                            v2 = 0.0f;
+                        }
+                    } else {
+                        free_move(p, x, v, v0, x2, v2);
+                    }
+                }
+                uint32_t kind = K_MOVE;
+                if (x2 >= (float)C) {
+                    if (en < 0) {
+                        kind = K_ARRIVE;
+                    } else {
+                        if (!near) En = d.edge[en];
+                        const uint32_t nle = (uint32_t)E_LANES(En);
+                        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
+                        const uint32_t tgt = En.w + ln;
+                        kind = K_CLAIM;
+                        d.scl[i] = tgt;
+                        d.sxo[i] = x;
+                        atomicMin(&d.claims[tgt], S.id[i]);
+                    }
+                }
+                const int32_t c2 = kind == K_MOVE ? (int32_t)x2 : c;
+                const uint32_t b2 = speed_byte(v2);
+                need_resolve = kind != K_MOVE || c2 != c || b2 != speed_byte(v);
+                rl = make_uint4(i, lb, (uint32_t)c | ((uint32_t)c2 << 16), b2 | (kind << 8));
+                S.x[i] = x2;
+                S.v[i] = v2;
+                S.m[i] = (m & M_REQ) | lane | (kind << M_KIND_SHIFT) | ((uint32_t)c << M_CELL_SHIFT);
+                // may want a lane change: wrong lane for the next edge, the
+                // direction allowed at this step, and within x0 of the end
+                if (p.lane_change && en >= 0) {
+                    const uint32_t req = (m & M_REQ) >> M_REQ_SHIFT;
+                    const bool dir_ok = (k & 1) == 0 ? req < lane : req > lane;
+                    lc_cand = dir_ok && ((float)C - x2 < p.x0);
                 }
             }
-            uint32_t kind = K_MOVE;
-            if (x2 >= (float)C) {
-                if (!have_route) {
-                    rp = S.rp[i];
-                    re = S.rend[i];
-                }
-                if (rp + 1 >= re) {
-                    kind = K_ARRIVE;
-                } else {
-                    const int32_t en = (int32_t)d.route[rp + 1];
-                    const uint4 En = d.edge[en];
-                    const int32_t nle = E_LANES(En);
-                    const int32_t ln = (int32_t)lane < nle - 1 ? (int32_t)lane : nle - 1;
-                    const uint32_t tgt = En.w + (uint32_t)ln;
-                    kind = K_CLAIM;
-                    d.scl[i] = tgt;
-                    d.sxo[i] = x;
-                    atomicMin(&d.claims[tgt], S.id[i]);
-                }
-            }
-            S.x[i] = x2;
-            S.v[i] = v2;
-            S.m[i] = lane | (kind << M_KIND_SHIFT) | ((uint32_t)c << M_CELL_SHIFT);
-        } else {
-            const uint32_t pos = wlo + (uint32_t)(it - n);
-            const uint32_t j = d.dep_order[pos];
-            if (d.status[j] != ST_WAIT) continue;
-            const uint32_t r0 = d.route_off[j];
-            const int32_t e0 = (int32_t)d.route[r0];
-            const uint4 E0 = d.edge[e0];
-            const uint32_t loc = j - d.scen_tbase[d.escen[e0]];
-            const int32_t l0 = (int32_t)(loc % (uint32_t)E_LANES(E0));
-            const bool ok = entry_free(d, E0, e0, l0);
-            d.dclaim[j] = ok ? 1 : 0;
-            if (ok) atomicMin(&d.claims[E0.w + (uint32_t)l0], j);
         }
+        const uint32_t r = wave_append(&s_rl, need_resolve);
+        if (need_resolve) d.rl_list[vlo + r] = rl;
+        const uint32_t q = wave_append(&s_lcc, lc_cand);
+        if (lc_cand) d.lcc_list[vlo + q] = i;
     }
     if (alive) atomicAdd(&cnt.c[P_VSTEPS], alive);
     if (scanned) atomicAdd(&cnt.c[P_SCAN], scanned);
     counts_flush(d, &cnt);
+    if (threadIdx.x == 0) {
+        d.rl_cnt[logical_block()] = s_rl;
+        d.lcc_cnt[logical_block()] = s_lcc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// departure candidates: due trips request their start lane (reads step k)
+
+__device__ __forceinline__ uint32_t n_candidates(const Dev &d, const Ctrl *ctl) {
+    return ctl->n_wq + (dep_hi_of(d, ctl->k) - ctl->dep_done);
+}
+
+__global__ __launch_bounds__(1024) void k_cand(Dev d) {
+    const Ctrl *ctl = d.ctrl;
+    const uint32_t nc = n_candidates(d, ctl);
+    const uint32_t W = (uint32_t)d.p.W;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += gridDim.x * blockDim.x) {
+        const uint32_t j = candidate(d, ctl, q);
+        if (d.status[j] != ST_WAIT) continue;
+        const uint4 o = d.orig[j];
+        const bool ok = !(d.aux[o.z] & AUX_BLOCKED) && first_occ(d.map, o.y, 0, (int32_t)W - 1) < 0;
+        d.dclaim[j] = ok ? 1 : 0;
+        if (ok) atomicMin(&d.claims[o.x], j);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -292,119 +438,161 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
 
 __global__ __launch_bounds__(1024) void k_resolve(Dev d) {
     __shared__ BlockCounts cnt;
-    __shared__ unsigned int s_wmin, s_arr, s_ev;
+    __shared__ unsigned int s_arr, s_ev;
     if (threadIdx.x == 0) {
-        s_wmin = 0xffffffffu;
         s_arr = 0;
         s_ev = 0;
     }
     counts_init(&cnt);
-    Ctrl *ctl = d.ctrl;
+    const Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
-    const uint32_t wlo = ctl->wait_lo;
-    const uint32_t dhi = dep_hi_of(d, k);
-    const uint32_t ncand = dhi > wlo ? dhi - wlo : 0;
-    const Slots S = d.buf[ctl->cur];
-    uint64_t lo, hi;
-    block_range((uint64_t)n + ncand, lo, hi);
-    for (uint64_t it = lo + threadIdx.x; it < hi; it += blockDim.x) {
-        if (it < n) {
-            const uint32_t i = (uint32_t)it;
-            const uint32_t m = S.m[i];
-            if (m & M_DEAD) continue;
-            const uint32_t kind = (m >> M_KIND_SHIFT) & 3u;
-            const uint32_t lane = m & M_LANE;
-            const int32_t oc = (int32_t)(m >> M_CELL_SHIFT);
-            const int32_t e = S.e[i];
-            const uint4 E = d.edge[e];
-            const int32_t C = E_CELLS(E);
-            uint8_t *lp = d.map + E.x + lane * (uint32_t)C;
-            if (kind == K_ARRIVE) {
-                lp[oc] = FREE_BYTE;
-                const uint32_t id = S.id[i];
-                d.status[id] = ST_DONE;
-                d.arrival[id] = k + 1;
-                add_exit(d, e, S.ent[i], k + 1);
-                S.m[i] = M_DEAD;
-                atomicAdd(&cnt.c[P_ARRIVED], 1u);
-                atomicAdd(&s_arr, 1u);
-                s_ev = 1;
-            } else if (kind == K_CLAIM) {
-                const uint32_t tgt = d.scl[i];
-                const uint32_t id = S.id[i];
-                if (d.claims[tgt] == id) {
-                    d.claims[tgt] = 0xffffffffu;
-                    lp[oc] = FREE_BYTE;
-                    const uint32_t rp = S.rp[i] + 1;
-                    const int32_t en = (int32_t)d.route[rp];
-                    const uint4 En = d.edge[en];
-                    const uint32_t ln = tgt - En.w;
-                    const float v2 = S.v[i];
-                    d.map[En.x + ln * (uint32_t)E_CELLS(En)] = speed_byte(v2);
-                    add_exit(d, e, S.ent[i], k + 1);
-                    add_entry(d, en, k + 1);
-                    S.e[i] = en;
-                    S.x[i] = 0.0f;
-                    S.rp[i] = rp;
-                    S.ent[i] = k + 1;
-                    S.m[i] = ln | M_ENTERED;
-                    atomicAdd(&cnt.c[P_TRANSFERS], 1u);
-                    s_ev = 1;
-                } else {
-                    const float xo = d.sxo[i];
-                    const float lim = (float)(C - 1);
-                    const float xn = xo > lim ? xo : lim;
-                    S.x[i] = xn;
-                    S.v[i] = 0.0f;
-                    const int32_t nc = (int32_t)xn;
-                    if (nc != oc) lp[oc] = FREE_BYTE;
-                    lp[nc] = speed_byte(0.0f);
-                    atomicAdd(&cnt.c[P_LOST], 1u);
-                }
-            } else {
-                const int32_t nc = (int32_t)S.x[i];
-                if (nc != oc) lp[oc] = FREE_BYTE;
-                lp[nc] = speed_byte(S.v[i]);
-            }
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    uint64_t lo64, hi64;
+    block_range(n, lo64, hi64);  // same share as this block had in the move phase
+    const uint32_t vlo = (uint32_t)lo64;
+    const uint32_t lb = logical_block();
+    const uint32_t nrl = d.rl_cnt[lb];
+    for (uint32_t it = threadIdx.x; it < nrl; it += blockDim.x) {
+        const uint4 r = d.rl_list[vlo + it];
+        const uint32_t kind = r.w >> 8;
+        const int32_t oc = (int32_t)(r.z & 0xffffu), nc = (int32_t)(r.z >> 16);
+        uint8_t *lp = d.map + r.y;
+        if (kind == K_MOVE) {
+            if (nc != oc) lp[oc] = FREE_BYTE;
+            lp[nc] = (uint8_t)(r.w & 0xffu);
+            continue;
+        }
+        const uint32_t i = r.x;
+        const int32_t e = S.e[i];
+        if (kind == K_ARRIVE) {
+            lp[oc] = FREE_BYTE;
+            const uint32_t id = S.id[i];
+            d.status[id] = ST_DONE;
+            d.arrival[id] = k + 1;
+            add_exit(d, e, S.ent[i], k + 1);
+            S.m[i] = M_DEAD;
+            atomicAdd(&cnt.c[P_ARRIVED], 1u);
+            atomicAdd(&s_arr, 1u);
+            s_ev = 1;
+            continue;
+        }
+        // entry request
+        const uint32_t tgt = d.scl[i];
+        const uint32_t id = S.id[i];
+        if (d.claims[tgt] == id) {
+            d.claims[tgt] = 0xffffffffu;
+            lp[oc] = FREE_BYTE;
+            const int32_t en = S.en[i];
+            const uint32_t rp = S.rp[i] + 1;
+            const uint32_t rend = S.rend[i];
+            const uint4 En = d.edge[en];
+            const uint32_t ln = tgt - En.w;
+            d.map[lane_base(En, ln)] = (uint8_t)(r.w & 0xffu);
+            add_exit(d, e, S.ent[i], k + 1);
+            add_entry(d, en, k + 1);
+            const int32_t en2 = rp + 1 < rend ? (int32_t)d.route[rp + 1] : -1;
+            const uint32_t req2 = en2 >= 0 ? required_lane(d, en2, E_LANES(En)) : 0u;
+            S.e[i] = en;
+            S.en[i] = en2;
+            S.x[i] = 0.0f;
+            S.rp[i] = rp;
+            S.ent[i] = k + 1;
+            S.m[i] = ln | M_ENTERED | (req2 << M_REQ_SHIFT);
+            atomicAdd(&cnt.c[P_TRANSFERS], 1u);
+            s_ev = 1;
         } else {
-            const uint32_t pos = wlo + (uint32_t)(it - n);
-            const uint32_t j = d.dep_order[pos];
-            if (d.status[j] != ST_WAIT) continue;
-            const uint32_t r0 = d.route_off[j];
-            const int32_t e0 = (int32_t)d.route[r0];
-            const uint4 E0 = d.edge[e0];
-            const uint32_t loc = j - d.scen_tbase[d.escen[e0]];
-            const uint32_t l0 = loc % (uint32_t)E_LANES(E0);
-            const uint32_t tgt = E0.w + l0;
-            if (d.claims[tgt] == j) {
-                d.claims[tgt] = 0xffffffffu;
-                d.status[j] = ST_ACTIVE;
-                const uint32_t ns = n + atomicAdd(&ctl->n_new, 1u);
-                S.x[ns] = 0.0f;
-                S.v[ns] = 0.0f;
-                S.e[ns] = e0;
-                S.m[ns] = l0 | M_ENTERED;
-                S.id[ns] = j;
-                S.rp[ns] = r0;
-                S.rend[ns] = d.route_off[j + 1];
-                S.ent[ns] = k + 1;
-                d.map[E0.x + l0 * (uint32_t)E_CELLS(E0)] = speed_byte(0.0f);
-                add_entry(d, e0, k + 1);
-                atomicAdd(&cnt.c[P_DEPARTS], 1u);
-                s_ev = 1;
-            } else {
-                if (d.dclaim[j]) atomicAdd(&cnt.c[P_LOST], 1u);
-                atomicMin(&s_wmin, pos);
-            }
+            const float xo = d.sxo[i];
+            const uint4 E = d.edge[e];
+            const float lim = (float)(E_CELLS(E) - 1);
+            const float xn = xo > lim ? xo : lim;
+            S.x[i] = xn;
+            S.v[i] = 0.0f;
+            const int32_t c2 = (int32_t)xn;
+            if (c2 != oc) lp[oc] = FREE_BYTE;
+            lp[c2] = speed_byte(0.0f);
+            atomicAdd(&cnt.c[P_LOST], 1u);
         }
     }
-    __syncthreads();
+    counts_flush(d, &cnt);
     if (threadIdx.x == 0) {
-        if (s_wmin != 0xffffffffu) atomicMin(&ctl->wait_lo_next, s_wmin);
-        if (s_arr) atomicAdd(&ctl->arr_step, s_arr);
-        if (s_ev) ctl->events = 1;
+        d.blk_arr[lb] = s_arr;
+        d.blk_ev[lb] = s_ev;
     }
+}
+
+// ---------------------------------------------------------------------------
+// depart: candidates that won their start lane become vehicles, the others
+// wait in the next queue.  Both lists are built with block-wide scans, so a
+// block makes one atomic per list per pass of 4096 candidates.
+
+__global__ __launch_bounds__(1024) void k_depart(Dev d) {
+    __shared__ BlockCounts cnt;
+    __shared__ uint32_t wsum[32];
+    __shared__ uint32_t s_base[2];
+    counts_init(&cnt);
+    Ctrl *ctl = d.ctrl;
+    const int32_t k = ctl->k;
+    const uint32_t nc = n_candidates(d, ctl);
+    const uint32_t n = ctl->n_slots;
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    uint32_t *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
+    bool any_dep = false;
+    for (uint32_t pass0 = blockIdx.x * blockDim.x; pass0 < nc; pass0 += gridDim.x * blockDim.x) {
+        const uint32_t q = pass0 + threadIdx.x;
+        uint32_t j = 0;
+        bool dep = false, rq = false;
+        uint4 o = make_uint4(0, 0, 0, 0);
+        if (q < nc) {
+            j = candidate(d, ctl, q);
+            if (d.status[j] == ST_WAIT) {
+                o = d.orig[j];
+                if (d.claims[o.x] == j) {
+                    d.claims[o.x] = 0xffffffffu;
+                    dep = true;
+                } else {
+                    if (d.dclaim[j]) atomicAdd(&cnt.c[P_LOST], 1u);
+                    rq = true;
+                }
+            }
+        }
+        uint32_t tot_dep, tot_rq;
+        const uint32_t my_dep = block_scan_1024(dep ? 1u : 0u, wsum, tot_dep);
+        __syncthreads();
+        const uint32_t my_rq = block_scan_1024(rq ? 1u : 0u, wsum, tot_rq);
+        if (threadIdx.x == 0) {
+            s_base[0] = tot_dep ? atomicAdd(&ctl->n_new, tot_dep) : 0u;
+            s_base[1] = tot_rq ? atomicAdd(&ctl->n_wq_next, tot_rq) : 0u;
+        }
+        __syncthreads();
+        if (rq) wq_next[s_base[1] + my_rq] = j;
+        if (dep) {
+            any_dep = true;
+            const uint32_t ns = n + s_base[0] + my_dep;
+            const int32_t e0 = (int32_t)o.z;
+            const uint32_t r0 = o.w;
+            const uint4 E0 = d.edge[e0];
+            const uint32_t l0 = o.x - E0.w;
+            const uint32_t rend = d.route_off[j + 1];
+            const int32_t en0 = r0 + 1 < rend ? (int32_t)d.route[r0 + 1] : -1;
+            const uint32_t req0 = en0 >= 0 ? required_lane(d, en0, E_LANES(E0)) : 0u;
+            d.status[j] = ST_ACTIVE;
+            S.x[ns] = 0.0f;
+            S.v[ns] = 0.0f;
+            S.e[ns] = e0;
+            S.en[ns] = en0;
+            S.m[ns] = l0 | M_ENTERED | (req0 << M_REQ_SHIFT);
+            S.id[ns] = j;
+            S.rp[ns] = r0;
+            S.rend[ns] = rend;
+            S.ent[ns] = k + 1;
+            d.map[o.y] = speed_byte(0.0f);
+            add_entry(d, e0, k + 1);
+            atomicAdd(&cnt.c[P_DEPARTS], 1u);
+        }
+        __syncthreads();
+    }
+    if (any_dep) ctl->dep_ev = 1;
     counts_flush(d, &cnt);
 }
 
@@ -413,164 +601,245 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d) {
 
 __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
     __shared__ BlockCounts cnt;
+    __shared__ uint32_t s_lc;
+    if (threadIdx.x == 0) s_lc = 0;
     counts_init(&cnt);
     Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
-    const uint32_t n = ctl->n_slots;  // vehicles that departed this step sit above n
-    const Slots S = d.buf[ctl->cur];
+    const uint32_t n = ctl->n_slots;
+    const uint32_t ncand_dep = ctl->n_wq + (dep_hi_of(d, k) - ctl->dep_done);
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
+    (void)ncand_dep;
     uint64_t lo, hi;
     block_range(n, lo, hi);
-    for (uint64_t it = lo + threadIdx.x; it < hi; it += blockDim.x) {
-        const uint32_t i = (uint32_t)it;
-        const uint32_t m = S.m[i];
-        if (m & (M_DEAD | M_ENTERED)) continue;
-        const float x = S.x[i];
-        const int32_t e = S.e[i];
-        const uint4 E = d.edge[e];
-        const int32_t C = E_CELLS(E);
-        const float dist = (float)C - x;
-        if (!(dist < p.x0)) continue;  // probability 0: no draw can succeed
-        const uint32_t rp = S.rp[i];
-        if (rp + 1 >= S.rend[i]) continue;  // last edge
-        const int32_t en = (int32_t)d.route[rp + 1];
-        const uint32_t ax = d.aux[en];
-        const int32_t rank = (int32_t)(ax & 0xffu), deg = (int32_t)((ax >> 8) & 0xffu);
-        const int32_t lane = (int32_t)(m & M_LANE);
-        const int32_t req = (rank * E_LANES(E)) / deg;
-        if (req == lane) continue;
-        const int32_t dir = req > lane ? 1 : -1;
-        if (((k & 1) == 0 && dir > 0) || ((k & 1) == 1 && dir < 0)) continue;
-        const float prob = 1.0f - dist / p.x0;
-        const int32_t sc = d.escen[e];
-        const uint32_t loc = S.id[i] - d.scen_tbase[sc];
-        const uint64_t h = mix64(d.scen_seed[sc] ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
-        if (!((float)(h >> 40) < prob * 16777216.0f)) continue;
-        atomicAdd(&cnt.c[P_LC_TRY], 1u);
-        const int32_t lt = lane + dir;
-        const int32_t c = (int32_t)x;
-        const uint8_t *lp = d.map + E.x + (uint32_t)lt * (uint32_t)C;
-        if (lp[c] != FREE_BYTE) continue;
-        const float v = S.v[i];
-        const int32_t D = E_LOOK(E);
-        bool ok = true;
-        const int32_t top = c + D < C - 1 ? c + D : C - 1;
-        const int32_t ca = first_occ(lp, c + 1, top);
-        if (ca >= 0) {
-            const float va = (float)lp[ca];
-            const float g_lead = ((float)ca - x) - p.L;
-            const float t = (p.al_i * v) - (p.al_a * va);
-            const float crit = p.g_a + (t > 0.0f ? t : 0.0f);
-            if (!(g_lead >= crit)) ok = false;
-        }
-        const int32_t bot = c - D > 0 ? c - D : 0;
-        const int32_t cb = last_occ(lp, c - 1, bot);
-        if (ok && cb >= 0) {
-            const float vb = (float)lp[cb];
-            const float g_lag = (x - p.L) - (float)(cb + 1);
-            const float t = (p.al_b * vb) - (p.al_i * v);
-            const float crit = p.g_b + (t > 0.0f ? t : 0.0f);
-            if (!(g_lag >= crit)) ok = false;
-        }
-        if (ok) {
-            S.m[i] = (uint32_t)lt | ((uint32_t)lane << M_OLDLANE_SHIFT);
-            d.lc_list[atomicAdd(&ctl->n_lc, 1u)] = i;
+    const uint32_t lb = logical_block();
+    const uint32_t ncand = d.lcc_cnt[lb];
+    for (uint32_t base = 0; base < ncand; base += blockDim.x) {
+        const uint32_t it = base + threadIdx.x;
+        bool accept = false;
+        uint32_t i = 0;
+        do {
+            if (it >= ncand) break;
+            i = d.lcc_list[lo + it];
+            const uint32_t m = S.m[i];
+            if (m & (M_DEAD | M_ENTERED)) break;  // entered its edge this step
+            const float x = S.x[i];
+            const int32_t e = S.e[i];
+            const uint4 E = d.edge[e];
+            const int32_t C = E_CELLS(E);
+            const float dist = (float)C - x;
+            if (!(dist < p.x0)) break;  // probability 0: no draw can succeed
+            const int32_t lane = (int32_t)(m & M_LANE);
+            const int32_t req = (int32_t)((m & M_REQ) >> M_REQ_SHIFT);
+            if (req == lane) break;
+            const int32_t dir = req > lane ? 1 : -1;
+            if (((k & 1) == 0 && dir > 0) || ((k & 1) == 1 && dir < 0)) break;
+            const float prob = 1.0f - dist / p.x0;
+            const int32_t sc = d.escen[e];
+            const uint32_t loc = S.id[i] - d.scen_tbase[sc];
+            const uint64_t h = mix64(d.scen_seed[sc] ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
+            if (!((float)(h >> 40) < prob * 16777216.0f)) break;
+            atomicAdd(&cnt.c[P_LC_TRY], 1u);
+            const int32_t lt = lane + dir;
+            const int32_t c = (int32_t)x;
+            const uint32_t lb = lane_base(E, (uint32_t)lt);
+            if (d.map[lb + (uint32_t)c] != FREE_BYTE) break;
+            const float v = S.v[i];
+            const int32_t D = E_LOOK(E);
+            const int32_t top = c + D < C - 1 ? c + D : C - 1;
+            const int32_t ca = first_occ(d.map, lb, c + 1, top);
+            if (ca >= 0) {
+                const float va = (float)d.map[lb + (uint32_t)ca];
+                const float g_lead = ((float)ca - x) - p.L;
+                const float t = (p.al_i * v) - (p.al_a * va);
+                const float crit = p.g_a + (t > 0.0f ? t : 0.0f);
+                if (!(g_lead >= crit)) break;
+            }
+            const int32_t bot = c - D > 0 ? c - D : 0;
+            const int32_t cb = last_occ(d.map, lb, bot, c - 1);
+            if (cb >= 0) {
+                const float vb = (float)d.map[lb + (uint32_t)cb];
+                const float g_lag = (x - p.L) - (float)(cb + 1);
+                const float t = (p.al_b * vb) - (p.al_i * v);
+                const float crit = p.g_b + (t > 0.0f ? t : 0.0f);
+                if (!(g_lag >= crit)) break;
+            }
+            S.m[i] = (uint32_t)lt | ((uint32_t)lane << M_OLDLANE_SHIFT) | (m & M_REQ);
+            accept = true;
+        } while (false);
+        const uint32_t q = wave_append(&s_lc, accept);
+        if (accept) {
+            d.lc_list[lo + q] = i;
             atomicAdd(&cnt.c[P_LC_OK], 1u);
         }
     }
     counts_flush(d, &cnt);
+    if (threadIdx.x == 0) d.lc_cnt[lb] = s_lc;
 }
 
 // ---------------------------------------------------------------------------
-// commit: lane changes into the map; the last block closes the step
-
-__device__ void end_of_step(const Dev &d) {
-    Ctrl *c = d.ctrl;
-    const int32_t k = c->k;
-    const uint32_t dhi = dep_hi_of(d, k);
-    const int64_t alive0 = c->n_alive;
-    c->watchdog = (alive0 > 0 && c->events == 0) ? c->watchdog + 1 : 0;
-    c->n_alive = alive0 + (int64_t)c->n_new - (int64_t)c->arr_step;
-    c->n_slots += c->n_new;
-    c->n_new = 0;
-    c->arr_step = 0;
-    c->n_lc = 0;
-    c->events = 0;
-    const uint32_t wn = c->wait_lo_next;
-    c->wait_lo = wn < dhi ? wn : dhi;
-    c->wait_lo_next = 0xffffffffu;
-    c->k = k + 1;
-}
+// commit: lane changes into the map
 
 __global__ __launch_bounds__(1024) void k_commit(Dev d) {
-    Ctrl *ctl = d.ctrl;
-    const uint32_t nlc = ctl->n_lc;
-    const Slots S = d.buf[ctl->cur];
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nlc; q += gridDim.x * blockDim.x) {
-        const uint32_t i = d.lc_list[q];
+    const Ctrl *ctl = d.ctrl;
+    const int32_t k = ctl->k;
+    const uint32_t n = ctl->n_slots;
+    const uint32_t ncand_dep = ctl->n_wq + (dep_hi_of(d, k) - ctl->dep_done);
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    (void)ncand_dep;
+    uint64_t lo, hi;
+    block_range(n, lo, hi);
+    const uint32_t nlc = d.lc_cnt[logical_block()];
+    for (uint32_t q = threadIdx.x; q < nlc; q += blockDim.x) {
+        const uint32_t i = d.lc_list[lo + q];
         const uint32_t m = S.m[i];
-        const uint32_t lt = m & M_LANE, lo = (m >> M_OLDLANE_SHIFT) & M_LANE;
+        const uint32_t lt = m & M_LANE, lold = (m >> M_OLDLANE_SHIFT) & M_LANE;
         const uint4 E = d.edge[S.e[i]];
-        const uint32_t C = (uint32_t)E_CELLS(E);
         const uint32_t c = (uint32_t)(int32_t)S.x[i];
-        d.map[E.x + lo * C + c] = FREE_BYTE;
-        d.map[E.x + lt * C + c] = speed_byte(S.v[i]);
-        S.m[i] = lt;
+        d.map[lane_base(E, lold) + c] = FREE_BYTE;
+        d.map[lane_base(E, lt) + c] = speed_byte(S.v[i]);
+        S.m[i] = lt | (m & M_REQ);
+    }
+}
+
+// end of step: one small block sums the per-block arrival and event flags
+// of the resolve phase and advances the clock and the lists
+__global__ __launch_bounds__(1024) void k_end(Dev d, uint32_t n_blocks) {
+    __shared__ uint32_t s_arr, s_ev;
+    if (threadIdx.x == 0) {
+        s_arr = 0;
+        s_ev = 0;
     }
     __syncthreads();
+    uint32_t arr = 0, ev = 0;
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+        arr += d.blk_arr[b];
+        ev |= d.blk_ev[b];
+    }
+    if (arr) atomicAdd(&s_arr, arr);
+    if (ev) s_ev = 1;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int t = atomicAdd(&ctl->done_commit, 1u);
-        if (t == gridDim.x - 1) {
-            __threadfence();
-            end_of_step(d);
-            ctl->done_commit = 0;
-        }
+        Ctrl *c = d.ctrl;
+        const int32_t k = c->k;
+        const int64_t alive0 = c->n_alive;
+        const bool ev = s_ev != 0 || c->dep_ev != 0;
+        c->watchdog = (alive0 > 0 && !ev) ? c->watchdog + 1 : 0;
+        c->dep_ev = 0;
+        c->n_alive = alive0 + (int64_t)c->n_new - (int64_t)s_arr;
+        c->n_slots += c->n_new;
+        c->n_new = 0;
+        c->dep_done = dep_hi_of(d, k);
+        c->wq_cur ^= 1u;
+        c->n_wq = c->n_wq_next;
+        c->n_wq_next = 0;
+        c->k = k + 1;
     }
 }
 
 // ---------------------------------------------------------------------------
-// compact: live slots of the current buffer -> the other buffer
+// reorder: counting sort of the live slots by edge into the other buffer
 
-__global__ __launch_bounds__(1024) void k_compact(Dev d) {
+__global__ __launch_bounds__(1024) void k_sort_count(Dev d) {
+    const Ctrl *ctl = d.ctrl;
+    const uint32_t n = ctl->n_slots;
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    uint64_t lo, hi;
+    block_range(n, lo, hi);
+    const uint32_t lane = lane_id();
+    for (uint64_t base = lo; base < hi; base += blockDim.x) {
+        const uint64_t it = base + threadIdx.x;
+        const uint32_t i = (uint32_t)it;
+        int32_t e = -1;
+        if (it < hi && !(S.m[i] & M_DEAD)) e = S.e[i];
+        // slots are mostly sorted by edge already: one atomic per run of
+        // equal edges inside the wavefront, not one per vehicle
+        const int32_t prev = __shfl_up(e, 1);
+        const bool head = lane == 0 || prev != e;
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint32_t hl = 63u - (uint32_t)__builtin_clzll(heads & upto);
+        const uint64_t after = heads & ~upto;
+        const uint32_t end = after ? (uint32_t)__builtin_ctzll(after) : 64u;
+        uint32_t b0 = 0;
+        if (lane == hl && e >= 0) b0 = atomicAdd(&d.ecnt[e], end - hl);
+        b0 = __shfl(b0, (int)hl);
+        if (e >= 0) d.srank[i] = b0 + (lane - hl);
+    }
+}
+
+// per 4096-edge chunk: exclusive offsets inside the chunk, chunk total; clears counts
+__global__ __launch_bounds__(1024) void k_sort_scan1(Dev d) {
+    __shared__ uint32_t wsum[32];
+    const uint32_t e0 = blockIdx.x * SORT_CHUNK + threadIdx.x * 4;
+    uint32_t c[4];
+    for (int j = 0; j < 4; ++j) c[j] = (e0 + j < (uint32_t)d.n_edges) ? d.ecnt[e0 + j] : 0u;
+    const uint32_t mine = c[0] + c[1] + c[2] + c[3];
+    uint32_t total;
+    uint32_t run = block_scan_1024(mine, wsum, total);
+    for (int j = 0; j < 4; ++j) {
+        if (e0 + j < (uint32_t)d.n_edges) {
+            d.eoff[e0 + j] = run;
+            d.ecnt[e0 + j] = 0;
+        }
+        run += c[j];
+    }
+    if (threadIdx.x == 0) d.csum[blockIdx.x] = total;
+}
+
+// exclusive scan of the chunk totals (one block); total live count -> ctrl
+__global__ __launch_bounds__(1024) void k_sort_scan2(Dev d, uint32_t n_chunks) {
+    __shared__ uint32_t wsum[32];
+    const uint32_t per = (n_chunks + 1023) / 1024;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < n_chunks) mine += d.csum[b0 + j];
+    uint32_t total;
+    uint32_t run = block_scan_1024(mine, wsum, total);
+    for (uint32_t j = 0; j < per; ++j) {
+        if (b0 + j < n_chunks) {
+            const uint32_t cj = d.csum[b0 + j];
+            d.csum[b0 + j] = run;
+            run += cj;
+        }
+    }
+    if (threadIdx.x == 0) d.ctrl->n_comp = total;
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scatter(Dev d) {
     Ctrl *ctl = d.ctrl;
     const uint32_t n = ctl->n_slots;
     const uint32_t cur = ctl->cur;
-    const Slots A = d.buf[cur], B = d.buf[cur ^ 1u];
+    const Slots A = cur ? d.buf[1] : d.buf[0];
+    const Slots B = cur ? d.buf[0] : d.buf[1];
     uint64_t lo, hi;
     block_range(n, lo, hi);
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint64_t base = lo; base < hi; base += blockDim.x) {
-        const uint64_t it = base + threadIdx.x;
-        const bool live = it < hi && !(A.m[(uint32_t)it] & M_DEAD);
-        const uint64_t mask = __ballot(live);
-        uint32_t dst = 0;
-        if (lane == 0 && mask) dst = atomicAdd(&ctl->n_comp, (uint32_t)__popcll(mask));
-        dst = __shfl(dst, 0);
-        if (live) {
-            const uint32_t i = (uint32_t)it;
-            const uint32_t o = dst + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            B.x[o] = A.x[i];
-            B.v[o] = A.v[i];
-            B.e[o] = A.e[i];
-            B.m[o] = A.m[i];
-            B.id[o] = A.id[i];
-            B.rp[o] = A.rp[i];
-            B.rend[o] = A.rend[i];
-            B.ent[o] = A.ent[i];
-        }
+    for (uint64_t it = lo + threadIdx.x; it < hi; it += blockDim.x) {
+        const uint32_t i = (uint32_t)it;
+        const uint32_t m = A.m[i];
+        if (m & M_DEAD) continue;
+        const int32_t e = A.e[i];
+        const uint32_t o = d.csum[(uint32_t)e / SORT_CHUNK] + d.eoff[e] + d.srank[i];
+        B.x[o] = A.x[i];
+        B.v[o] = A.v[i];
+        B.e[o] = e;
+        B.en[o] = A.en[i];
+        B.m[o] = m;
+        B.id[o] = A.id[i];
+        B.rp[o] = A.rp[i];
+        B.rend[o] = A.rend[i];
+        B.ent[o] = A.ent[i];
     }
-    __syncthreads();
+}
+
+__global__ void k_sort_finish(Dev d) {
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int t = atomicAdd(&ctl->done_compact, 1u);
-        if (t == gridDim.x - 1) {
-            __threadfence();
-            ctl->n_slots = ctl->n_comp;
-            ctl->n_comp = 0;
-            ctl->cur = cur ^ 1u;
-            ctl->done_compact = 0;
-        }
+        Ctrl *c = d.ctrl;
+        c->n_slots = c->n_comp;
+        c->n_comp = 0;
+        c->cur ^= 1u;
     }
 }
 
@@ -579,6 +848,16 @@ __global__ __launch_bounds__(1024) void k_compact(Dev d) {
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s) {
     hipLaunchKernelGGL(k_move, dim3(blocks), dim3(threads), 0, s, d);
 }
+void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s) {
+    (void)blocks;
+    (void)threads;
+    hipLaunchKernelGGL(k_cand, dim3(CAND_BLOCKS * 4), dim3(256), 0, s, d);
+}
+void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s) {
+    (void)blocks;
+    (void)threads;
+    hipLaunchKernelGGL(k_depart, dim3(CAND_BLOCKS), dim3(1024), 0, s, d);
+}
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s) {
     hipLaunchKernelGGL(k_resolve, dim3(blocks), dim3(threads), 0, s, d);
 }
@@ -586,10 +865,16 @@ void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s) {
     hipLaunchKernelGGL(k_lanechg, dim3(blocks), dim3(threads), 0, s, d);
 }
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_commit, dim3(blocks), dim3(threads), 0, s, d);
+    if (d.p.lane_change) hipLaunchKernelGGL(k_commit, dim3(blocks), dim3(threads), 0, s, d);
+    hipLaunchKernelGGL(k_end, dim3(1), dim3(1024), 0, s, d, (uint32_t)blocks);
 }
-void launch_compact(const Dev &d, int blocks, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(threads), 0, s, d);
+void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s) {
+    const uint32_t n_chunks = ((uint32_t)d.n_edges + SORT_CHUNK - 1) / SORT_CHUNK;
+    hipLaunchKernelGGL(k_sort_count, dim3(blocks), dim3(threads), 0, s, d);
+    hipLaunchKernelGGL(k_sort_scan1, dim3(n_chunks), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_sort_scan2, dim3(1), dim3(1024), 0, s, d, n_chunks);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(blocks), dim3(threads), 0, s, d);
+    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, d);
 }
 
 }  // namespace lpsim
