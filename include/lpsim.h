@@ -209,6 +209,20 @@ int32_t lpsim_block_edge(lpsim_ctx *ctx, int32_t edge, int32_t on);
 int32_t lpsim_set_launch(lpsim_ctx *ctx, int32_t block_size, int32_t n_blocks,
                          int32_t graph_steps);
 
+/* Autotuner: times n_steps from the current state for every pair
+ * (block_sizes[i], block_counts[j]) on an internal stream with HIP events,
+ * rewinding to the same state before each trial and after the last, then
+ * keeps the fastest pair (graph_steps unchanged).  Results do not depend on
+ * the launch shape, so only the speed changes.
+ *   best_out     host, 3 int32: best block size, block count, and the trial
+ *                time in microseconds per step (rounded)
+ *   trial_us     host, n_bs*n_bc doubles (microseconds per step), or NULL
+ * Errors: ESTATE, EINVAL (a shape outside lpsim_set_launch's limits), ENOMEM,
+ * EDEVICE. */
+int32_t lpsim_autotune(lpsim_ctx *ctx, int32_t n_steps, const int32_t *block_sizes, int32_t n_bs,
+                       const int32_t *block_counts, int32_t n_bc, int32_t *best_out,
+                       double *trial_us);
+
 /* Kernel timing for measurement: when on, lpsim_step launches kernels one by
  * one and records a HIP event pair around each on the work stream;
  * lpsim_kernel_times then returns the summed milliseconds and launch counts
@@ -225,6 +239,57 @@ int32_t lpsim_kernel_times(lpsim_ctx *ctx, double *ms_out, int64_t *launches_out
 int32_t lpsim_state_size(lpsim_ctx *ctx, size_t *bytes);
 int32_t lpsim_save_state(lpsim_ctx *ctx, void *host_buf, size_t bytes);
 int32_t lpsim_restore_state(lpsim_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* ------------------------------------------------------------------------
+ * Learned edge travel-time surrogate (the traffic-assignment use of the
+ * simulator's output; the paper's title and abstract name traffic assignment
+ * and travel-time estimation, it gives no surrogate): a perceptron
+ *   x[32] -> 256 -> 256 -> 256 -> y[16], ReLU on the hidden layers,
+ * bfloat16 operands on the matrix cores with binary32 accumulation; hidden
+ * activations are rounded to bfloat16 (nearest even) after bias and ReLU.
+ * All pointers are DEVICE pointers owned by the caller; `stream` is a
+ * hipStream_t or NULL (the null stream); calls only enqueue work.
+ * bfloat16 values are passed as uint16_t bit patterns.
+ * Layer l maps in_l -> out_l with (in, out) = (32,256), (256,256), (256,256),
+ * (256,16).  "wt" layout = [out_l][in_l] (forward); "w" layout = [in_l][out_l]
+ * (backward); biases [out_l] binary32.
+ * Errors: EINVAL (null pointer, negative size), EDEVICE (launch failure).
+ * ------------------------------------------------------------------------ */
+
+/* Fixed shape of the perceptron (any pointer may be NULL). */
+int32_t lpsim_mlp_shape(int32_t *in_dim, int32_t *hidden, int32_t *out_dim);
+
+/* y[n][16] = MLP(x[n][32]).  h: NULL, or 3 pointers to [n][256] bfloat16
+ * buffers that receive the hidden activations (needed by the backward). */
+int32_t lpsim_mlp_forward(const uint16_t *x, const uint16_t *const *wt, const float *const *bias, float *y,
+                          uint16_t *const *h, int64_t n, void *stream);
+
+/* Masked mean-squared-error gradient: dz_out[i] = bfloat16(2 (y[i] - t[i]) *
+ * inv_count) where mask[i] (or every i if mask is NULL), else 0, over the
+ * n*16 outputs; loss_sum (nullable) accumulates sum (y - t)^2 * inv_count. */
+int32_t lpsim_mlp_loss_grad(const float *y, const float *target, const uint8_t *mask, int64_t n,
+                            float inv_count, uint16_t *dz_out, float *loss_sum, void *stream);
+
+/* Bytes of the `workspace` that lpsim_mlp_backward needs for n_split batch
+ * slices (binary32 partial sums, reduced in a fixed order). */
+size_t lpsim_mlp_workspace_bytes(int32_t n_split);
+
+/* Backward pass of the binary32-accumulated perceptron for a batch of n rows:
+ * x and h (3 pointers) as produced by the forward, dz_out[n][16] bfloat16
+ * output gradient, w (4 pointers, "w" layout bfloat16).  Writes dwt (4
+ * pointers, "wt" layout binary32) and db (4 pointers).  dz_scratch: 2*n*256
+ * bfloat16.  Deterministic for fixed n_split. */
+int32_t lpsim_mlp_backward(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                           const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
+                           float *workspace, int32_t n_split, int64_t n, void *stream);
+
+/* Adam step (Kingma & Ba) on one binary32 matrix [rows][cols] ("wt" layout;
+ * a bias is rows = 1): m, v moment buffers, t = step count from 1.  Also
+ * writes the bfloat16 copies wt_bf16 ([rows][cols]) and w_bf16 ([cols][rows]),
+ * either may be NULL. */
+int32_t lpsim_mlp_adam(float *w, uint16_t *wt_bf16, uint16_t *w_bf16, const float *grad, float *m, float *v,
+                       int32_t rows, int32_t cols, float lr, float beta1, float beta2, float eps, int32_t t,
+                       void *stream);
 
 /* Derived constants: 0 -> entry window W (cells), 1 -> look-ahead D (cells)
  * of scenario 0, 2 -> steps per statistics bin. */

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblpsim.so")
 
-SOURCES = ["lpsim_kernels.hip", "lpsim_host.cpp"]
+SOURCES = ["lpsim_kernels.hip", "lpsim_host.cpp", "mlp_kernels.hip", "mlp_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

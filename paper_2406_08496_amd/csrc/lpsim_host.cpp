@@ -1093,6 +1093,73 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     return LPSIM_OK;
 }
 
+int32_t lpsim_autotune(lpsim_ctx *c, int32_t n_steps, const int32_t *block_sizes, int32_t n_bs,
+                       const int32_t *block_counts, int32_t n_bc, int32_t *best_out, double *trial_us) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if (n_steps < 1 || n_bs < 1 || n_bc < 1 || !block_sizes || !block_counts || !best_out)
+        return fail(c, LPSIM_EINVAL, "bad autotune arguments");
+    for (int32_t i = 0; i < n_bs; ++i)
+        if (block_sizes[i] < 64 || block_sizes[i] > 1024 || block_sizes[i] % 64)
+            return fail(c, LPSIM_EINVAL, "bad block size %d", block_sizes[i]);
+    for (int32_t j = 0; j < n_bc; ++j)
+        if (block_counts[j] < 8 || block_counts[j] > MAX_BLOCKS || block_counts[j] % 8)
+            return fail(c, LPSIM_EINVAL, "bad block count %d", block_counts[j]);
+    if (c->timing) return fail(c, LPSIM_ESTATE, "turn kernel timing off before autotuning");
+    size_t bytes = 0;
+    if ((rc = lpsim_state_size(c, &bytes))) return rc;
+    std::vector<uint8_t> snap;
+    try {
+        snap.resize(bytes);
+    } catch (...) {
+        return fail(c, LPSIM_ENOMEM, "no host memory for the autotune snapshot");
+    }
+    if ((rc = lpsim_save_state(c, snap.data(), bytes))) return rc;
+    const int keep_threads = c->threads, keep_blocks = c->blocks;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    HIPCHK(c, hipEventCreate(&t0));
+    HIPCHK(c, hipEventCreate(&t1));
+    double best = 1e300;
+    int best_t = keep_threads, best_b = keep_blocks;
+    for (int32_t i = 0; i < n_bs; ++i) {
+        for (int32_t j = 0; j < n_bc; ++j) {
+            c->threads = block_sizes[i];
+            c->blocks = block_counts[j];
+            drop_graphs(c);
+            if ((rc = lpsim_restore_state(c, snap.data(), bytes))) break;
+            // one untimed graph replay to build and warm the graphs, then rewind
+            if ((rc = lpsim_step(c, std::min(n_steps, std::max(c->graph_steps, 1)), c->own))) break;
+            if ((rc = lpsim_restore_state(c, snap.data(), bytes))) break;
+            HIPCHK(c, hipEventRecord(t0, c->own));
+            if ((rc = lpsim_step(c, n_steps, c->own))) break;
+            HIPCHK(c, hipEventRecord(t1, c->own));
+            HIPCHK(c, hipEventSynchronize(t1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, t0, t1));
+            const double us = 1000.0 * (double)ms / n_steps;
+            if (trial_us) trial_us[i * n_bc + j] = us;
+            if (us < best) {
+                best = us;
+                best_t = c->threads;
+                best_b = c->blocks;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    c->threads = rc ? keep_threads : best_t;
+    c->blocks = rc ? keep_blocks : best_b;
+    drop_graphs(c);
+    int32_t rc2 = lpsim_restore_state(c, snap.data(), bytes);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    best_out[0] = best_t;
+    best_out[1] = best_b;
+    best_out[2] = (int32_t)std::lround(best);
+    return LPSIM_OK;
+}
+
 int32_t lpsim_query(const lpsim_ctx *c, int32_t which) {
     if (!c) return LPSIM_EINVAL;
     if (which == 0) return c->dp.W;

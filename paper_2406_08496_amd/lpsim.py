@@ -74,6 +74,14 @@ SIGNATURES = {
     "lpsim_save_state": ([_vp, _vp, ctypes.c_size_t], _i32),
     "lpsim_restore_state": ([_vp, _vp, ctypes.c_size_t], _i32),
     "lpsim_query": ([_vp, _i32], _i32),
+    "lpsim_autotune": ([_vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
+    "lpsim_mlp_shape": ([_vp, _vp, _vp], _i32),
+    "lpsim_mlp_forward": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
+    "lpsim_mlp_loss_grad": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], _i32),
+    "lpsim_mlp_workspace_bytes": ([_i32], ctypes.c_size_t),
+    "lpsim_mlp_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
+    "lpsim_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, ctypes.c_float, _i32, _vp], _i32),
     "lpsim_last_error": ([_vp], ctypes.c_char_p),
 }
 
@@ -201,6 +209,19 @@ class Simulator:
 
     def step(self, n=1, stream=None):
         self._check(load_library().lpsim_step(self._h, int(n), _stream_handle(stream)))
+
+    def autotune(self, n_steps=64, block_sizes=(128, 256, 512, 1024),
+                 block_counts=(512, 1024, 2048, 4096)):
+        """Pick the fastest launch shape on the current state (state unchanged)."""
+        bs = np.ascontiguousarray(block_sizes, np.int32)
+        bc = np.ascontiguousarray(block_counts, np.int32)
+        best = np.zeros(3, np.int32)
+        trials = np.zeros(len(bs) * len(bc), np.float64)
+        self._check(load_library().lpsim_autotune(self._h, int(n_steps), _p(bs), len(bs), _p(bc),
+                                                  len(bc), _p(best), _p(trials)))
+        return {"block_size": int(best[0]), "blocks": int(best[1]),
+                "us_per_step": {(int(b), int(g)): float(trials[i * len(bc) + j])
+                                for i, b in enumerate(bs) for j, g in enumerate(bc)}}
 
     def set_timing(self, on=True):
         self._check(load_library().lpsim_set_timing(self._h, 1 if on else 0))

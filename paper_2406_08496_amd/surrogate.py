@@ -1,0 +1,141 @@
+"""Edge travel-time surrogate: the perceptron of the library, driven from Python.
+
+Weights and activations live in torch tensors on the GPU (PyTorch provides
+device memory and the stream); every arithmetic step -- forward, loss
+gradient, backward, Adam -- runs in the library's HIP kernels through the C
+ABI (`lpsim_mlp_*`).  bfloat16 tensors are passed by their bit patterns.
+
+Shape: x[32] -> 256 -> 256 -> 256 -> y[16]; layer l "wt" = [out_l][in_l].
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from .lpsim import LpsimError, load_library
+
+IN, HID, OUT = 32, 256, 16
+DIMS = [(IN, HID), (HID, HID), (HID, HID), (HID, OUT)]
+
+
+def _ptrs(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise LpsimError(rc, what)
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class EdgeMLP:
+    """Binary32 master weights, bfloat16 copies in both layouts, Adam state."""
+
+    def __init__(self, wt=None, b=None, seed=0, device="cuda", n_split=8):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.n_split = n_split
+        if wt is None:
+            rng = np.random.default_rng(seed)
+            wt = [rng.normal(0.0, np.sqrt(2.0 / i), size=(o, i)) for i, o in DIMS]
+            b = [np.zeros(o) for _, o in DIMS]
+        self.w = [torch.tensor(np.asarray(x, np.float32), device=device) for x in wt]
+        self.b = [torch.tensor(np.asarray(x, np.float32), device=device) for x in b]
+        self.m_w = [torch.zeros_like(x) for x in self.w]
+        self.v_w = [torch.zeros_like(x) for x in self.w]
+        self.m_b = [torch.zeros_like(x) for x in self.b]
+        self.v_b = [torch.zeros_like(x) for x in self.b]
+        self.g_w = [torch.zeros_like(x) for x in self.w]
+        self.g_b = [torch.zeros_like(x) for x in self.b]
+        self.t = 0
+        self.lib = load_library()
+        self._sync_bf16()
+        self._ws = None
+
+    def _sync_bf16(self):
+        # bfloat16 copies of the binary32 master, written by the optimizer
+        # kernel with a zero step (w - 0 * update == w)
+        torch = self.torch
+        self.wt_bf = [torch.empty(x.shape, dtype=torch.bfloat16, device=self.device) for x in self.w]
+        self.w_bf = [torch.empty((x.shape[1], x.shape[0]), dtype=torch.bfloat16, device=self.device)
+                     for x in self.w]
+        f = ctypes.c_float
+        for l, (i, o) in enumerate(DIMS):
+            m = torch.zeros_like(self.w[l])
+            _check(self.lib.lpsim_mlp_adam(
+                ctypes.c_void_p(self.w[l].data_ptr()), ctypes.c_void_p(self.wt_bf[l].data_ptr()),
+                ctypes.c_void_p(self.w_bf[l].data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(m.data_ptr()), o, i, f(0.0), f(0.9),
+                f(0.999), f(1e-8), 1, _stream()), "mlp bf16 copy")
+
+    # -- inference ----------------------------------------------------------
+    def forward(self, x, keep=False):
+        """x: [n][32] bfloat16 tensor -> y [n][16] float32 (and hidden if keep)."""
+        torch = self.torch
+        assert x.dtype == torch.bfloat16 and x.shape[1] == IN and x.is_contiguous()
+        n = x.shape[0]
+        y = torch.empty((n, OUT), dtype=torch.float32, device=self.device)
+        hs = [torch.empty((n, HID), dtype=torch.bfloat16, device=self.device) for _ in range(3)] if keep else None
+        h_arr = _ptrs(hs) if keep else None
+        _check(self.lib.lpsim_mlp_forward(ctypes.c_void_p(x.data_ptr()), _ptrs(self.wt_bf), _ptrs(self.b),
+                                          ctypes.c_void_p(y.data_ptr()), h_arr, n, _stream()), "mlp forward")
+        return (y, hs) if keep else y
+
+    # -- training ------------------------------------------------------------
+    def gradients(self, x, target, mask=None):
+        """Loss (masked MSE) and gradients into self.g_w / self.g_b."""
+        torch = self.torch
+        n = x.shape[0]
+        y, hs = self.forward(x, keep=True)
+        dz = torch.empty((n, OUT), dtype=torch.bfloat16, device=self.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        count = int(mask.sum().item()) if mask is not None else n * OUT
+        inv = 1.0 / max(count, 1)
+        mptr = ctypes.c_void_p(mask.data_ptr()) if mask is not None else None
+        _check(self.lib.lpsim_mlp_loss_grad(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                            mptr, n, ctypes.c_float(inv), ctypes.c_void_p(dz.data_ptr()),
+                                            ctypes.c_void_p(loss.data_ptr()), _stream()), "mlp loss")
+        self.backward(x, hs, dz)
+        return loss, y
+
+    def backward(self, x, hs, dz):
+        torch = self.torch
+        n = x.shape[0]
+        nbytes = self.lib.lpsim_mlp_workspace_bytes(self.n_split)
+        if self._ws is None or self._ws.numel() * 4 < nbytes:
+            self._ws = torch.empty(nbytes // 4, dtype=torch.float32, device=self.device)
+        scratch = torch.empty((2, n, HID), dtype=torch.bfloat16, device=self.device)
+        _check(self.lib.lpsim_mlp_backward(ctypes.c_void_p(x.data_ptr()), _ptrs(hs), ctypes.c_void_p(dz.data_ptr()),
+                                           _ptrs(self.w_bf), _ptrs(self.g_w), _ptrs(self.g_b),
+                                           ctypes.c_void_p(scratch.data_ptr()), ctypes.c_void_p(self._ws.data_ptr()),
+                                           self.n_split, n, _stream()), "mlp backward")
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        f = ctypes.c_float
+        for l, (i, o) in enumerate(DIMS):
+            _check(self.lib.lpsim_mlp_adam(
+                ctypes.c_void_p(self.w[l].data_ptr()), ctypes.c_void_p(self.wt_bf[l].data_ptr()),
+                ctypes.c_void_p(self.w_bf[l].data_ptr()), ctypes.c_void_p(self.g_w[l].data_ptr()),
+                ctypes.c_void_p(self.m_w[l].data_ptr()), ctypes.c_void_p(self.v_w[l].data_ptr()),
+                o, i, f(lr), f(beta1), f(beta2), f(eps), self.t, _stream()), "mlp adam")
+            _check(self.lib.lpsim_mlp_adam(
+                ctypes.c_void_p(self.b[l].data_ptr()), None, None, ctypes.c_void_p(self.g_b[l].data_ptr()),
+                ctypes.c_void_p(self.m_b[l].data_ptr()), ctypes.c_void_p(self.v_b[l].data_ptr()),
+                1, o, f(lr), f(beta1), f(beta2), f(eps), self.t, _stream()), "mlp adam")
+
+    def train_step(self, x, target, mask=None, lr=1e-3):
+        loss, _ = self.gradients(x, target, mask)
+        self.adam_step(lr=lr)
+        return loss

@@ -199,3 +199,19 @@ def test_batch_equals_solo(Sim):
         assert_same_state({k: vb[k][t0:t1] for k in vb}, vr, f"scenario {s}")
         sr = ref.edge_stats()
         assert_same_stats({k: sb[k][e0:e1] for k in sb}, sr, f"scenario {s}")
+
+
+def test_autotune_keeps_state(Sim):
+    case("autotune mid-run, then continue; vs a plain run")
+    inst = synth.grid_instance(seed=51, side=6, n_trips=1500, depart_window=400, len_lo=20, len_hi=150)
+    a = Sim().load(inst)
+    a.step(500)
+    res = a.autotune(n_steps=40, block_sizes=(64, 256), block_counts=(8, 64, 512))
+    assert res["block_size"] in (64, 256) and res["blocks"] in (8, 64, 512)
+    assert len(res["us_per_step"]) == 6
+    a.step(700)
+    b = Sim().load(inst)
+    b.step(1200)
+    assert_same_state(a.vehicles(), b.vehicles(), "autotuned")
+    assert_same_stats(a.edge_stats(), b.edge_stats(), "autotuned")
+    assert_same_counters(a.counters(), b.counters(), "autotuned")
