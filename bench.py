@@ -43,6 +43,9 @@ def log(*a):
 def make_workload(name):
     from paper_2406_08496_amd import synth
 
+    if name.startswith("batch"):
+        n = int(name.split(":")[1]) if ":" in name else 64
+        return synth.batch_scenarios(n), 48
     if name == "regional":
         return synth.regional(), 48
     if name == "tiny":
@@ -82,6 +85,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--assign", type=int, default=0,
+                    help="also run N MSA iterations, plain vs surrogate (regional workload)")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -96,17 +102,41 @@ def main():
     torch.cuda.set_device(0)
     t = time.perf_counter()
     inst, n_bins = make_workload(args.workload)
-    K = args.steps if args.steps is not None else inst.n_steps
+    batch = isinstance(inst, list)
+    if batch:
+        insts = inst
+        name = f"batch-{len(insts)}-scenarios"
+        n_nodes = sum(i.n_nodes for i in insts)
+        n_edges = sum(i.n_edges for i in insts)
+        n_trips = sum(i.n_trips for i in insts)
+        n_route = sum(int(i.route_off[-1]) for i in insts)
+        horizon = max(i.n_steps for i in insts)
+    else:
+        name, n_nodes, n_edges, n_trips = inst.name, inst.n_nodes, inst.n_edges, inst.n_trips
+        n_route, horizon = int(inst.route_off[-1]), inst.n_steps
+    K = args.steps if args.steps is not None else horizon
     W = args.warmup
-    log(f"workload {inst.name}: {inst.n_nodes} nodes, {inst.n_edges} edges, {inst.n_trips} trips, "
-        f"{int(inst.route_off[-1])} route entries; generated in {time.perf_counter() - t:.1f} s")
+    log(f"workload {name}: {n_nodes} nodes, {n_edges} edges, {n_trips} trips, "
+        f"{n_route} route entries; generated in {time.perf_counter() - t:.1f} s")
 
     t = time.perf_counter()
     sim = Simulator(n_bins=n_bins)
     sim.set_launch(args.block, args.blocks, args.graph_steps)
-    sim.load(inst)
+    if batch:
+        sim.load_batch(insts)
+    else:
+        sim.load(inst)
     log(f"loaded in {time.perf_counter() - t:.1f} s")
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.autotune:
+        # tune on a loaded state (a third of the horizon in), then rewind
+        snap = sim.save_state()
+        sim.step(horizon // 3)
+        tuned = sim.autotune(n_steps=64)
+        sim.restore_state(snap)
+        log(f"autotuned: block {tuned['block_size']}, blocks {tuned['blocks']}")
+        tuned = {"block": tuned["block_size"], "blocks": tuned["blocks"]}
     # warm-up steps (graph capture, caches), then rewind to step 0
     snap0 = sim.save_state()
     if W:
@@ -127,7 +157,7 @@ def main():
     vsteps = c["vehicle_steps"]
     value = vsteps / (ms / 1e3)
     log(f"timed {K} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), {vsteps} vehicle-steps, "
-        f"arrived {c['arrived']}/{inst.n_trips}, active {c['active']}, watchdog {c['watchdog']}")
+        f"arrived {c['arrived']}/{n_trips}, active {c['active']}, watchdog {c['watchdog']}")
 
     out = {
         "metric": "vehicle-steps/sec at 2.8M trips",
@@ -142,9 +172,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded planar graph + gravity demand standing in for SF Bay / SFCTA)",
-        "config": {"workload": inst.name, "nodes": inst.n_nodes, "edges": inst.n_edges,
-                   "trips": inst.n_trips, "dt": 0.5, "horizon_steps": inst.n_steps,
-                   "block": args.block, "blocks": args.blocks, "graph_steps": args.graph_steps},
+        "config": {"workload": name, "nodes": n_nodes, "edges": n_edges,
+                   "trips": n_trips, "dt": 0.5, "horizon_steps": horizon,
+                   "block": tuned["block"] if tuned else args.block,
+                   "blocks": tuned["blocks"] if tuned else args.blocks, "graph_steps": args.graph_steps},
         "trips_per_s": c["arrived"] / (ms / 1e3),
         "arrived": c["arrived"],
         "vehicle_steps": vsteps,
@@ -175,10 +206,33 @@ def main():
         out["dominant_kernel"] = dom
         log("kernel times:", json.dumps(out["kernel_ms"]))
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not batch:
         out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget)
         log("cpu baseline:", json.dumps(out["cpu_baseline"]))
+    if args.assign and not batch:
+        out["assignment"] = run_assignment(inst, args.assign)
     print(json.dumps(out), flush=True)
+
+
+def run_assignment(inst, n_iter):
+    """MSA with the full simulation every iteration vs surrogate-assisted MSA
+    (full simulation every 5th iteration as judge and training data), same
+    GPU; wall times include routing, simulation, loading and training."""
+    from paper_2406_08496_amd.assign import Assignment, agreement
+
+    a = Assignment(inst, n_bins=48)
+    plain = a.run_plain(n_iter)
+    log(f"plain MSA: {plain['wall_s']:.1f} s, timings {a.timings}")
+    del a
+    b = Assignment(inst, n_bins=48)
+    sur = b.run_surrogate(n_iter)
+    log(f"surrogate MSA: {sur['wall_s']:.1f} s, timings {b.timings}, history {sur['hist']}")
+    g = agreement(sur["tt"], plain["tt"], plain["exits"])
+    n_sur = sum(1 for h in sur["hist"] if h["mode"] == "surrogate")
+    return {"iterations": n_iter, "plain_wall_s": plain["wall_s"], "surrogate_wall_s": sur["wall_s"],
+            "speedup": plain["wall_s"] / sur["wall_s"], "final_tt_rel_l2": g,
+            "surrogate_iterations": n_sur, "judge_errors": [h.get("judge_err") for h in sur["hist"]
+                                                            if "judge_err" in h]}
 
 
 if __name__ == "__main__":

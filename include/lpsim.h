@@ -291,6 +291,68 @@ int32_t lpsim_mlp_adam(float *w, uint16_t *wt_bf16, uint16_t *w_bf16, const floa
                        int32_t rows, int32_t cols, float lr, float beta1, float beta2, float eps, int32_t t,
                        void *stream);
 
+/* ------------------------------------------------------------------------
+ * Traffic assignment around the simulator (the paper's title names traffic
+ * assignment; routes are the simulator's input,
+ * Section 3.1 vehicle data).  The method of successive averages alternates
+ * evaluation of edge travel times (full simulation, or the surrogate) with
+ * shortest-time routing.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lpsim_router lpsim_router;
+
+/* Router over a directed graph (host arrays, copied).  n_threads <= 0 uses
+ * every hardware thread.  Errors: EINVAL, ENOMEM. */
+int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src, const int32_t *dst,
+                            int32_t n_threads, lpsim_router **out);
+void lpsim_router_destroy(lpsim_router *r);
+
+/* Shortest-time route of every trip origin[i] -> dest[i] (host arrays) for
+ * the edge costs `cost` (host, seconds, finite and > 0), by backward Dijkstra
+ * per distinct destination in float64; among equally short choices the lower
+ * edge id is taken.  Errors: EINVAL (bad ids, origin == destination,
+ * unreachable destination, bad cost), ENOMEM. */
+int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                           const int32_t *dest);
+
+/* Write the routes of the last solve (host buffers).  take_new (n_trips
+ * flags) NULL takes every new route; otherwise trip i keeps its old route
+ * (old_off / old_edges) where take_new[i] == 0.  out_off receives n_trips+1
+ * offsets; out_edges (may be NULL to size the result first) the edge ids.
+ * Errors: ESTATE (no solve), EINVAL. */
+int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t *old_edges, const uint8_t *take_new,
+                          int64_t *out_off, int32_t *out_edges);
+
+/* Network loading for the surrogate (device arrays): each trip walks its
+ * route from step depart+1, spending max(1, round(tt_steps[e][bin])) steps on
+ * an edge entered in `bin`, until `horizon`.  Writes entries per entry bin
+ * (inflow_bin, [E][B] int32) and vehicle-steps per bin (occ_steps_bin,
+ * [E][B] int64), both zeroed first; exact integers.  route_off [n+1] int64,
+ * route_edges int32 (input edge ids). */
+int32_t lpsim_surrogate_load(const int64_t *route_off, const int32_t *route_edges, const int32_t *depart_step,
+                             int64_t n_trips, const float *tt_steps, int32_t n_edges, int32_t n_bins,
+                             int32_t bin_steps, int32_t horizon, int32_t *inflow_bin, int64_t *occ_steps_bin,
+                             void *stream);
+
+/* Perceptron inputs for every (edge, window of 12 bins), device arrays:
+ * x_out [E * B/12][32] bfloat16 = log1p(inflow) x12, occupancy / (bin_steps *
+ * ceil(length) * lanes) * jam_spacing x12, log(length), lanes/4, speed/22.4,
+ * zeros.  n_bins must be a multiple of 12. */
+int32_t lpsim_surrogate_features(int32_t n_edges, int32_t n_bins, int32_t bin_steps, float jam_spacing,
+                                 const int32_t *inflow_bin, const int64_t *occ_steps_bin, const float *length_m,
+                                 const uint8_t *lanes, const float *speed_mps, uint16_t *x_out, void *stream);
+
+/* Training targets from simulator statistics (device arrays):
+ * y_out [E * B/12][16] = log(tt_sum_bin / exits_bin / tt_free_steps) per bin
+ * of the window, mask_out 1 where exits_bin > 0 (outputs 12..15 masked). */
+int32_t lpsim_surrogate_targets(int32_t n_edges, int32_t n_bins, const int32_t *exits_bin, const int64_t *tt_sum_bin,
+                                const float *tt_free_steps, float *y_out, uint8_t *mask_out, void *stream);
+
+/* Damped travel-time update from predictions (device arrays):
+ * tt_steps[e][b] <- (1-damping) tt + damping clamp(tt_free exp(y), 1, tt_max). */
+int32_t lpsim_surrogate_tt(int32_t n_edges, int32_t n_bins, const float *y_pred, const float *tt_free_steps,
+                           float damping, float tt_max, float *tt_steps, void *stream);
+
 /* Derived constants: 0 -> entry window W (cells), 1 -> look-ahead D (cells)
  * of scenario 0, 2 -> steps per statistics bin. */
 int32_t lpsim_query(const lpsim_ctx *ctx, int32_t which);

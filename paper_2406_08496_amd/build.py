@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblpsim.so")
 
-SOURCES = ["lpsim_kernels.hip", "lpsim_host.cpp", "mlp_kernels.hip", "mlp_host.cpp"]
+SOURCES = ["lpsim_kernels.hip", "lpsim_host.cpp", "mlp_kernels.hip", "mlp_host.cpp",
+           "surrogate_kernels.hip", "assign_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -33,7 +34,7 @@ def build_lib(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + [
         "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
-        *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp,
+        *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp, "-lpthread",
     ]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

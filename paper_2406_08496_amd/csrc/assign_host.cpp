@@ -1,0 +1,232 @@
+// assign_host.cpp -- static shortest-time routing for the traffic-assignment
+// loop (the paper's title: accelerated traffic assignment; routes are the
+// simulator's input, Section 3.1 vehicle data).
+//
+// For every distinct destination a backward Dijkstra (binary heap, float64
+// costs) gives, for every node, the edge to take toward that destination.
+// Among equally short choices the lower edge id wins, which makes the result
+// independent of heap order and of the number of threads.  Destinations are
+// spread over std::thread workers.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lpsim.h"
+
+struct lpsim_router {
+    int32_t n_nodes = 0, n_edges = 0, n_threads = 1;
+    std::vector<int32_t> src, dst;
+    std::vector<int64_t> in_off;   // incoming edges per node (CSR)
+    std::vector<int32_t> in_edges;
+    // last solve
+    std::vector<int32_t> dests;      // distinct destination nodes
+    std::vector<int32_t> dest_idx;   // per trip
+    std::vector<int32_t> origin;     // per trip
+    std::vector<int32_t> next_edge;  // [dest][node]
+    std::vector<int32_t> len;        // per trip, new route length
+    bool solved = false;
+};
+
+namespace {
+
+struct HeapItem {
+    double key;
+    int32_t node;
+};
+
+void tree_to(const lpsim_router &r, const double *cost, int32_t target, int32_t *nx, std::vector<double> &dist,
+             std::vector<uint8_t> &done, std::vector<HeapItem> &heap) {
+    const int32_t n = r.n_nodes;
+    std::fill(dist.begin(), dist.end(), std::numeric_limits<double>::infinity());
+    std::fill(done.begin(), done.end(), 0);
+    for (int32_t u = 0; u < n; ++u) nx[u] = -1;
+    auto cmp = [](const HeapItem &a, const HeapItem &b) { return a.key > b.key; };
+    heap.clear();
+    dist[target] = 0.0;
+    heap.push_back({0.0, target});
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        const HeapItem it = heap.back();
+        heap.pop_back();
+        const int32_t y = it.node;
+        if (done[y]) continue;
+        done[y] = 1;
+        for (int64_t j = r.in_off[y]; j < r.in_off[y + 1]; ++j) {
+            const int32_t e = r.in_edges[j];
+            const int32_t x = r.src[e];
+            if (done[x]) continue;
+            const double cand = dist[y] + cost[e];
+            if (cand < dist[x] || (cand == dist[x] && e < nx[x])) {
+                dist[x] = cand;
+                nx[x] = e;
+                heap.push_back({cand, x});
+                std::push_heap(heap.begin(), heap.end(), cmp);
+            }
+        }
+    }
+}
+
+template <class F>
+void parallel_for(int32_t n_items, int32_t n_threads, F &&f) {
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const int32_t i = next.fetch_add(1);
+            if (i >= n_items) break;
+            f(i);
+        }
+    };
+    const int32_t nt = std::max(1, std::min(n_threads, n_items));
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src, const int32_t *dst,
+                            int32_t n_threads, lpsim_router **out) {
+    if (!out || n_nodes <= 0 || n_edges <= 0 || !src || !dst) return LPSIM_EINVAL;
+    *out = nullptr;
+    for (int32_t e = 0; e < n_edges; ++e)
+        if (src[e] < 0 || src[e] >= n_nodes || dst[e] < 0 || dst[e] >= n_nodes) return LPSIM_EINVAL;
+    lpsim_router *r = new (std::nothrow) lpsim_router();
+    if (!r) return LPSIM_ENOMEM;
+    try {
+        r->n_nodes = n_nodes;
+        r->n_edges = n_edges;
+        r->n_threads = n_threads > 0 ? n_threads : (int32_t)std::max(1u, std::thread::hardware_concurrency());
+        r->src.assign(src, src + n_edges);
+        r->dst.assign(dst, dst + n_edges);
+        r->in_off.assign((size_t)n_nodes + 1, 0);
+        for (int32_t e = 0; e < n_edges; ++e) r->in_off[(size_t)dst[e] + 1]++;
+        for (int32_t u = 0; u < n_nodes; ++u) r->in_off[(size_t)u + 1] += r->in_off[(size_t)u];
+        r->in_edges.resize((size_t)n_edges);
+        std::vector<int64_t> pos(r->in_off.begin(), r->in_off.end() - 1);
+        for (int32_t e = 0; e < n_edges; ++e) r->in_edges[(size_t)pos[(size_t)dst[e]]++] = e;
+    } catch (...) {
+        delete r;
+        return LPSIM_ENOMEM;
+    }
+    *out = r;
+    return LPSIM_OK;
+}
+
+void lpsim_router_destroy(lpsim_router *r) { delete r; }
+
+int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                           const int32_t *dest) {
+    if (!r || !cost || n_trips < 0 || (n_trips > 0 && (!origin || !dest))) return LPSIM_EINVAL;
+    for (int32_t e = 0; e < r->n_edges; ++e)
+        if (!(cost[e] > 0.0) || !std::isfinite(cost[e])) return LPSIM_EINVAL;
+    r->solved = false;
+    try {
+        std::unordered_map<int32_t, int32_t> idx;
+        r->dests.clear();
+        r->dest_idx.resize((size_t)n_trips);
+        r->origin.assign(origin, origin + n_trips);
+        for (int64_t i = 0; i < n_trips; ++i) {
+            const int32_t t = dest[i];
+            if (t < 0 || t >= r->n_nodes || origin[i] < 0 || origin[i] >= r->n_nodes || origin[i] == t)
+                return LPSIM_EINVAL;
+            auto it = idx.find(t);
+            if (it == idx.end()) {
+                it = idx.emplace(t, (int32_t)r->dests.size()).first;
+                r->dests.push_back(t);
+            }
+            r->dest_idx[(size_t)i] = it->second;
+        }
+        const int32_t nd = (int32_t)r->dests.size();
+        r->next_edge.assign((size_t)nd * r->n_nodes, -1);
+        const int32_t nw = std::max(1, std::min(r->n_threads, nd));
+        std::vector<std::vector<double>> dist(nw, std::vector<double>((size_t)r->n_nodes));
+        std::vector<std::vector<uint8_t>> done(nw, std::vector<uint8_t>((size_t)r->n_nodes));
+        std::vector<std::vector<HeapItem>> heap(nw);
+        std::atomic<int32_t> next{0};
+        auto worker = [&](int32_t w) {
+            for (;;) {
+                const int32_t d = next.fetch_add(1);
+                if (d >= nd) break;
+                tree_to(*r, cost, r->dests[(size_t)d], r->next_edge.data() + (size_t)d * r->n_nodes, dist[w],
+                        done[w], heap[w]);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int32_t w = 1; w < nw; ++w) pool.emplace_back(worker, w);
+        worker(0);
+        for (auto &t : pool) t.join();
+        // route lengths
+        r->len.assign((size_t)n_trips, 0);
+        std::atomic<int> bad{0};
+        const int64_t chunk = 65536;
+        const int32_t n_chunks = (int32_t)((n_trips + chunk - 1) / chunk);
+        parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
+            for (int64_t i = ci * chunk; i < std::min<int64_t>(n_trips, (ci + 1) * chunk); ++i) {
+                const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+                const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
+                int32_t u = r->origin[(size_t)i], l = 0;
+                while (u != t) {
+                    const int32_t e = nx[u];
+                    if (e < 0 || l > r->n_nodes) {
+                        bad = 1;
+                        break;
+                    }
+                    u = r->dst[(size_t)e];
+                    ++l;
+                }
+                r->len[(size_t)i] = l;
+            }
+        });
+        if (bad) return LPSIM_EINVAL;  // some destination unreachable
+    } catch (...) {
+        return LPSIM_ENOMEM;
+    }
+    r->solved = true;
+    return LPSIM_OK;
+}
+
+int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t *old_edges, const uint8_t *take_new,
+                          int64_t *out_off, int32_t *out_edges) {
+    if (!r || !r->solved || !out_off) return LPSIM_ESTATE;
+    const int64_t n = (int64_t)r->len.size();
+    if (take_new && (!old_off || !old_edges)) return LPSIM_EINVAL;
+    out_off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const bool nw = !take_new || take_new[i];
+        const int64_t l = nw ? r->len[(size_t)i] : old_off[i + 1] - old_off[i];
+        out_off[i + 1] = out_off[i] + l;
+    }
+    if (!out_edges) return LPSIM_OK;
+    const int64_t chunk = 65536;
+    const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
+    parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
+        for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
+            int32_t *o = out_edges + out_off[i];
+            if (take_new && !take_new[i]) {
+                std::memcpy(o, old_edges + old_off[i], (size_t)(old_off[i + 1] - old_off[i]) * 4);
+                continue;
+            }
+            const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+            const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
+            int32_t u = r->origin[(size_t)i];
+            while (u != t) {
+                const int32_t e = nx[u];
+                *o++ = e;
+                u = r->dst[(size_t)e];
+            }
+        }
+    });
+    return LPSIM_OK;
+}
+
+}  // extern "C"

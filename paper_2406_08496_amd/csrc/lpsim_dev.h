@@ -70,7 +70,16 @@ struct Slots {
     uint32_t *rp;   // absolute route index of the current edge
     uint32_t *rend; // absolute route end (exclusive)
     int32_t *ent;   // step the current edge was entered
+    // per-vehicle copies of what the move phase needs, refreshed when the
+    // vehicle enters an edge or changes lane (saves dependent loads)
+    uint32_t *lb;   // lane-map offset of the vehicle's lane
+    uint32_t *cd;   // cells | look-ahead << 16 of the current edge
+    float *v0;      // speed limit of the current edge
+    uint32_t *tlb;  // lane-map offset of the entry lane on the next edge (NO_NEXT on the last edge)
+    uint32_t *tgt;  // claim word of that entry lane
 };
+
+constexpr uint32_t NO_NEXT = 0xffffffffu;
 
 struct Dev {
     Params p;

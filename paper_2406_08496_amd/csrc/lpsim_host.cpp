@@ -503,6 +503,11 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         if ((rc = alloc_n(c, s.rp, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.rend, cap, c->trip_allocs))) return rc;
         if ((rc = alloc_n(c, s.ent, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.lb, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.cd, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.v0, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.tlb, cap, c->trip_allocs))) return rc;
+        if ((rc = alloc_n(c, s.tgt, cap, c->trip_allocs))) return rc;
     }
     if ((rc = alloc_n(c, d.scl, cap, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.sxo, cap, c->trip_allocs))) return rc;
@@ -984,7 +989,7 @@ struct SnapHeader {
 static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_wq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)MAX_BLOCKS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
-           E * 12 + E * B * 24 + (size_t)n_slots * 36 + (size_t)n_wq * 4;
+           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (size_t)n_wq * 4;
 }
 
 int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
@@ -1038,6 +1043,11 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = get(S.rp, n * 4))) return rc;
     if ((rc = get(S.rend, n * 4))) return rc;
     if ((rc = get(S.ent, n * 4))) return rc;
+    if ((rc = get(S.lb, n * 4))) return rc;
+    if ((rc = get(S.cd, n * 4))) return rc;
+    if ((rc = get(S.v0, n * 4))) return rc;
+    if ((rc = get(S.tlb, n * 4))) return rc;
+    if ((rc = get(S.tgt, n * 4))) return rc;
     if ((rc = get(d.wq[ct.wq_cur], (size_t)ct.n_wq * 4))) return rc;
     return LPSIM_OK;
 }
@@ -1085,6 +1095,11 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(S.rp, n * 4))) return rc;
     if ((rc = put(S.rend, n * 4))) return rc;
     if ((rc = put(S.ent, n * 4))) return rc;
+    if ((rc = put(S.lb, n * 4))) return rc;
+    if ((rc = put(S.cd, n * 4))) return rc;
+    if ((rc = put(S.v0, n * 4))) return rc;
+    if ((rc = put(S.tlb, n * 4))) return rc;
+    if ((rc = put(S.tgt, n * 4))) return rc;
     if ((rc = put(d.wq[0], (size_t)h.n_wq * 4))) return rc;
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));

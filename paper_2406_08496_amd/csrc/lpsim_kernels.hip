@@ -101,8 +101,10 @@ __device__ __forceinline__ uint64_t occ_bits(uint64_t w, uint32_t base, uint32_t
     return t;
 }
 
-// first occupied cell in [lo, hi] of the lane starting at map offset `lane`, or -1
-__device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi) {
+// first occupied cell in [lo, hi] of the lane starting at map offset `lane`,
+// or -1; *val receives its byte (the occupant's shown speed)
+__device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                             uint32_t *val = nullptr) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
     for (uint32_t a = s & ~15u; a <= e; a += 64) {
@@ -114,17 +116,27 @@ __device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, 
         for (uint32_t j = 0; j < nch; ++j) {
             const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
             const uint32_t b = a + 16 * j;
-            uint64_t t = occ_bits((uint64_t)c.x | ((uint64_t)c.y << 32), b, s, e);
-            if (t) return (int32_t)(b + ((uint32_t)__builtin_ctzll(t) >> 3) - lane);
-            t = occ_bits((uint64_t)c.z | ((uint64_t)c.w << 32), b + 8, s, e);
-            if (t) return (int32_t)(b + 8 + ((uint32_t)__builtin_ctzll(t) >> 3) - lane);
+            const uint64_t w0 = (uint64_t)c.x | ((uint64_t)c.y << 32), w1 = (uint64_t)c.z | ((uint64_t)c.w << 32);
+            uint64_t t = occ_bits(w0, b, s, e);
+            if (t) {
+                const uint32_t k = (uint32_t)__builtin_ctzll(t) >> 3;
+                if (val) *val = (uint32_t)(w0 >> (8 * k)) & 0xffu;
+                return (int32_t)(b + k - lane);
+            }
+            t = occ_bits(w1, b + 8, s, e);
+            if (t) {
+                const uint32_t k = (uint32_t)__builtin_ctzll(t) >> 3;
+                if (val) *val = (uint32_t)(w1 >> (8 * k)) & 0xffu;
+                return (int32_t)(b + 8 + k - lane);
+            }
         }
     }
     return -1;
 }
 
-// highest occupied cell in [lo, hi], or -1
-__device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi) {
+// highest occupied cell in [lo, hi], or -1; *val receives its byte
+__device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                            uint32_t *val = nullptr) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
     const uint32_t first = s & ~15u;
@@ -137,10 +149,19 @@ __device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, i
         for (uint32_t j = 0; j < nch; ++j) {
             const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
             const uint32_t b = (uint32_t)a - 16 * j;
-            uint64_t t = occ_bits((uint64_t)c.z | ((uint64_t)c.w << 32), b + 8, s, e);
-            if (t) return (int32_t)(b + 8 + ((63u - (uint32_t)__builtin_clzll(t)) >> 3) - lane);
-            t = occ_bits((uint64_t)c.x | ((uint64_t)c.y << 32), b, s, e);
-            if (t) return (int32_t)(b + ((63u - (uint32_t)__builtin_clzll(t)) >> 3) - lane);
+            const uint64_t w0 = (uint64_t)c.x | ((uint64_t)c.y << 32), w1 = (uint64_t)c.z | ((uint64_t)c.w << 32);
+            uint64_t t = occ_bits(w1, b + 8, s, e);
+            if (t) {
+                const uint32_t k = (63u - (uint32_t)__builtin_clzll(t)) >> 3;
+                if (val) *val = (uint32_t)(w1 >> (8 * k)) & 0xffu;
+                return (int32_t)(b + 8 + k - lane);
+            }
+            t = occ_bits(w0, b, s, e);
+            if (t) {
+                const uint32_t k = (63u - (uint32_t)__builtin_clzll(t)) >> 3;
+                if (val) *val = (uint32_t)(w0 >> (8 * k)) & 0xffu;
+                return (int32_t)(b + k - lane);
+            }
         }
     }
     return -1;
@@ -291,6 +312,25 @@ __device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int3
 // ---------------------------------------------------------------------------
 // move: longitudinal intent from step-k state
 
+// refresh a vehicle's cached edge data: it is on edge `e` (record E) in
+// `lane`, next edge `en` (-1 on the last edge)
+__device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t i, const uint4 &E, uint32_t lane,
+                                          int32_t en) {
+    S.lb[i] = lane_base(E, lane);
+    S.cd[i] = (uint32_t)E_CELLS(E) | ((uint32_t)E_LOOK(E) << 16);
+    S.v0[i] = __uint_as_float(E.z);
+    if (en >= 0) {
+        const uint4 En = d.edge[en];
+        const uint32_t nle = (uint32_t)E_LANES(En);
+        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
+        S.tlb[i] = lane_base(En, ln);
+        S.tgt[i] = En.w + ln;
+    } else {
+        S.tlb[i] = NO_NEXT;
+        S.tgt[i] = 0;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_move(Dev d) {
     __shared__ BlockCounts cnt;
     __shared__ uint32_t s_rl, s_lcc;
@@ -314,31 +354,28 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
         bool need_resolve = false, lc_cand = false;
         uint4 rl = make_uint4(0, 0, 0, 0);
         if (it < nv) {
+            // one round of independent, coalesced loads of the vehicle's state
             const uint32_t m = S.m[i];
+            const float x = S.x[i], v = S.v[i];
+            const uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i], id = S.id[i];
+            const float v0 = S.v0[i];
+            const int32_t en = S.en[i];
             if (!(m & M_DEAD)) {
                 ++alive;
-                const float x = S.x[i], v = S.v[i];
-                const int32_t e = S.e[i], en = S.en[i];
                 const uint32_t lane = m & M_LANE;
-                const uint4 E = d.edge[e];
-                const int32_t C = E_CELLS(E), D = E_LOOK(E);
-                const float v0 = __uint_as_float(E.z);
-                const uint32_t lb = lane_base(E, lane);
+                const int32_t C = (int32_t)(cd & 0xffffu), D = (int32_t)(cd >> 16);
                 const int32_t c = (int32_t)x;
                 // stop line inside the look-ahead: the next edge's entry matters
-                const bool near = en >= 0 && c + D >= C;
-                uint4 En = make_uint4(0, 0, 0, 0);
+                const bool near = tlb != NO_NEXT && c + D >= C;
                 uint32_t ax_en = 0;
-                if (near) {
-                    En = d.edge[en];
-                    ax_en = d.aux[en];
-                }
+                if (near) ax_en = d.aux[en];
                 const int32_t top = c + D < C - 1 ? c + D : C - 1;
-                const int32_t cl = first_occ(d.map, lb, c + 1, top);
+                uint32_t vlb = 0;
+                const int32_t cl = first_occ(d.map, lb, c + 1, top, &vlb);
                 scanned += (uint32_t)((cl >= 0 ? cl : top) - c);
                 float x2, v2;
                 if (cl >= 0) {
-                    const float vl = (float)d.map[lb + (uint32_t)cl];
+                    const float vl = (float)vlb;
                     const float gap = ((float)cl - x) - p.L;
                     idm_follow(p, x, v, v0, gap, vl, x2, v2);
                     const float lim = (float)cl - p.L;
@@ -349,11 +386,9 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
                 } else {
                     bool stop = false;
                     if (near) {
-                        const uint32_t nle = (uint32_t)E_LANES(En);
-                        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
-                        stop = (ax_en & AUX_BLOCKED) || first_occ(d.map, lane_base(En, ln), 0, p.W - 1) >= 0;
-                        // next edge record (16), its flags (4), entry window
-                        scanned += 20u + (uint32_t)p.W;
+                        stop = (ax_en & AUX_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
+                        // next edge's flags (4) and entry window
+                        scanned += 4u + (uint32_t)p.W;
                     }
                     if (stop) {
                         const float gap = (float)C - x;
@@ -369,17 +404,14 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
                 }
                 uint32_t kind = K_MOVE;
                 if (x2 >= (float)C) {
-                    if (en < 0) {
+                    if (tlb == NO_NEXT) {
                         kind = K_ARRIVE;
                     } else {
-                        if (!near) En = d.edge[en];
-                        const uint32_t nle = (uint32_t)E_LANES(En);
-                        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
-                        const uint32_t tgt = En.w + ln;
+                        const uint32_t tgt = S.tgt[i];
                         kind = K_CLAIM;
                         d.scl[i] = tgt;
                         d.sxo[i] = x;
-                        atomicMin(&d.claims[tgt], S.id[i]);
+                        atomicMin(&d.claims[tgt], id);
                     }
                 }
                 const int32_t c2 = kind == K_MOVE ? (int32_t)x2 : c;
@@ -391,7 +423,7 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
                 S.m[i] = (m & M_REQ) | lane | (kind << M_KIND_SHIFT) | ((uint32_t)c << M_CELL_SHIFT);
                 // may want a lane change: wrong lane for the next edge, the
                 // direction allowed at this step, and within x0 of the end
-                if (p.lane_change && en >= 0) {
+                if (p.lane_change && tlb != NO_NEXT) {
                     const uint32_t req = (m & M_REQ) >> M_REQ_SHIFT;
                     const bool dir_ok = (k & 1) == 0 ? req < lane : req > lane;
                     lc_cand = dir_ok && ((float)C - x2 < p.x0);
@@ -499,12 +531,12 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d) {
             S.rp[i] = rp;
             S.ent[i] = k + 1;
             S.m[i] = ln | M_ENTERED | (req2 << M_REQ_SHIFT);
+            set_cache(d, S, i, En, ln, en2);
             atomicAdd(&cnt.c[P_TRANSFERS], 1u);
             s_ev = 1;
         } else {
             const float xo = d.sxo[i];
-            const uint4 E = d.edge[e];
-            const float lim = (float)(E_CELLS(E) - 1);
+            const float lim = (float)((int32_t)(S.cd[i] & 0xffffu) - 1);
             const float xn = xo > lim ? xo : lim;
             S.x[i] = xn;
             S.v[i] = 0.0f;
@@ -586,6 +618,7 @@ __global__ __launch_bounds__(1024) void k_depart(Dev d) {
             S.rp[ns] = r0;
             S.rend[ns] = rend;
             S.ent[ns] = k + 1;
+            set_cache(d, S, ns, E0, l0, en0);
             d.map[o.y] = speed_byte(0.0f);
             add_entry(d, e0, k + 1);
             atomicAdd(&cnt.c[P_DEPARTS], 1u);
@@ -623,11 +656,11 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             if (it >= ncand) break;
             i = d.lcc_list[lo + it];
             const uint32_t m = S.m[i];
-            if (m & (M_DEAD | M_ENTERED)) break;  // entered its edge this step
-            const float x = S.x[i];
+            const float x = S.x[i], v = S.v[i];
+            const uint32_t cd = S.cd[i], lb0 = S.lb[i], id = S.id[i];
             const int32_t e = S.e[i];
-            const uint4 E = d.edge[e];
-            const int32_t C = E_CELLS(E);
+            if (m & (M_DEAD | M_ENTERED)) break;  // entered its edge this step
+            const int32_t C = (int32_t)(cd & 0xffffu);
             const float dist = (float)C - x;
             if (!(dist < p.x0)) break;  // probability 0: no draw can succeed
             const int32_t lane = (int32_t)(m & M_LANE);
@@ -637,29 +670,30 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             if (((k & 1) == 0 && dir > 0) || ((k & 1) == 1 && dir < 0)) break;
             const float prob = 1.0f - dist / p.x0;
             const int32_t sc = d.escen[e];
-            const uint32_t loc = S.id[i] - d.scen_tbase[sc];
+            const uint32_t loc = id - d.scen_tbase[sc];
             const uint64_t h = mix64(d.scen_seed[sc] ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
             if (!((float)(h >> 40) < prob * 16777216.0f)) break;
             atomicAdd(&cnt.c[P_LC_TRY], 1u);
             const int32_t lt = lane + dir;
             const int32_t c = (int32_t)x;
-            const uint32_t lb = lane_base(E, (uint32_t)lt);
-            if (d.map[lb + (uint32_t)c] != FREE_BYTE) break;
-            const float v = S.v[i];
-            const int32_t D = E_LOOK(E);
+            const uint32_t lb = lb0 + (uint32_t)(dir * C);  // lane lt of the same edge
+            const int32_t D = (int32_t)(cd >> 16);
+            uint32_t vtmp = 0;
             const int32_t top = c + D < C - 1 ? c + D : C - 1;
-            const int32_t ca = first_occ(d.map, lb, c + 1, top);
+            // the target cell itself, then the lead and lag gaps
+            if (first_occ(d.map, lb, c, c) >= 0) break;
+            const int32_t ca = first_occ(d.map, lb, c + 1, top, &vtmp);
             if (ca >= 0) {
-                const float va = (float)d.map[lb + (uint32_t)ca];
+                const float va = (float)vtmp;
                 const float g_lead = ((float)ca - x) - p.L;
                 const float t = (p.al_i * v) - (p.al_a * va);
                 const float crit = p.g_a + (t > 0.0f ? t : 0.0f);
                 if (!(g_lead >= crit)) break;
             }
             const int32_t bot = c - D > 0 ? c - D : 0;
-            const int32_t cb = last_occ(d.map, lb, bot, c - 1);
+            const int32_t cb = last_occ(d.map, lb, bot, c - 1, &vtmp);
             if (cb >= 0) {
-                const float vb = (float)d.map[lb + (uint32_t)cb];
+                const float vb = (float)vtmp;
                 const float g_lag = (x - p.L) - (float)(cb + 1);
                 const float t = (p.al_b * vb) - (p.al_i * v);
                 const float crit = p.g_b + (t > 0.0f ? t : 0.0f);
@@ -695,11 +729,22 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d) {
         const uint32_t i = d.lc_list[lo + q];
         const uint32_t m = S.m[i];
         const uint32_t lt = m & M_LANE, lold = (m >> M_OLDLANE_SHIFT) & M_LANE;
-        const uint4 E = d.edge[S.e[i]];
+        const uint32_t C = S.cd[i] & 0xffffu;
+        const uint32_t lb_old = S.lb[i];
+        const uint32_t lb_new = lb_old + (lt - lold) * C;  // unsigned wrap handles lt < lold
         const uint32_t c = (uint32_t)(int32_t)S.x[i];
-        d.map[lane_base(E, lold) + c] = FREE_BYTE;
-        d.map[lane_base(E, lt) + c] = speed_byte(S.v[i]);
+        d.map[lb_old + c] = FREE_BYTE;
+        d.map[lb_new + c] = speed_byte(S.v[i]);
         S.m[i] = lt | (m & M_REQ);
+        S.lb[i] = lb_new;
+        const int32_t en = S.en[i];
+        if (en >= 0) {  // entry lane on the next edge follows the lane index
+            const uint4 En = d.edge[en];
+            const uint32_t nle = (uint32_t)E_LANES(En);
+            const uint32_t ln = lt < nle - 1 ? lt : nle - 1;
+            S.tlb[i] = lane_base(En, ln);
+            S.tgt[i] = En.w + ln;
+        }
     }
 }
 
@@ -831,6 +876,11 @@ __global__ __launch_bounds__(1024) void k_sort_scatter(Dev d) {
         B.rp[o] = A.rp[i];
         B.rend[o] = A.rend[i];
         B.ent[o] = A.ent[i];
+        B.lb[o] = A.lb[i];
+        B.cd[o] = A.cd[i];
+        B.v0[o] = A.v0[i];
+        B.tlb[o] = A.tlb[i];
+        B.tgt[o] = A.tgt[i];
     }
 }
 

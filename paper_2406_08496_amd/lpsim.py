@@ -75,6 +75,14 @@ SIGNATURES = {
     "lpsim_restore_state": ([_vp, _vp, ctypes.c_size_t], _i32),
     "lpsim_query": ([_vp, _i32], _i32),
     "lpsim_autotune": ([_vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
+    "lpsim_router_create": ([_i32, _i32, _vp, _vp, _i32, ctypes.POINTER(_vp)], _i32),
+    "lpsim_router_destroy": ([_vp], None),
+    "lpsim_router_solve": ([_vp, _vp, _i64, _vp, _vp], _i32),
+    "lpsim_router_fill": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "lpsim_surrogate_load": ([_vp, _vp, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
+    "lpsim_surrogate_features": ([_i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "lpsim_surrogate_targets": ([_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "lpsim_surrogate_tt": ([_i32, _i32, _vp, _vp, ctypes.c_float, ctypes.c_float, _vp, _vp], _i32),
     "lpsim_mlp_shape": ([_vp, _vp, _vp], _i32),
     "lpsim_mlp_forward": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "lpsim_mlp_loss_grad": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], _i32),

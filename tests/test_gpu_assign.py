@@ -1,0 +1,117 @@
+"""Surrogate data path and assignment loop on the GPU, against the oracle.
+
+Loading is integer work and must match exactly; features are float32 results
+rounded to bfloat16 and must match the float64 oracle within one bfloat16
+step; targets and the damped travel-time update within float32 rounding."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import assign as oa
+from oracle import mlp
+from paper_2406_08496_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def case(*a):
+    print("CASE:", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("seed,n_bins,bin_steps,horizon", [(1, 12, 50, 700), (2, 24, 30, 400)])
+def test_load_exact(torch, seed, n_bins, bin_steps, horizon):
+    case("surrogate loading", seed, n_bins, bin_steps, horizon)
+    from paper_2406_08496_amd.lpsim import load_library
+
+    lib = load_library()
+    inst = synth.grid_instance(seed=seed, side=5, n_trips=400, depart_window=300)
+    rng = np.random.default_rng(seed)
+    tt = rng.uniform(0.2, 60.0, size=(inst.n_edges, n_bins)).astype(np.float32)
+    tt[rng.random(tt.shape) < 0.05] = 2.5  # exact ties of the rounding rule
+    inflow_ref, occ_ref = oa.load(inst.route_off, inst.route_edges, inst.depart_step, tt, n_bins, bin_steps, horizon)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    inflow = torch.empty((inst.n_edges, n_bins), dtype=torch.int32, device="cuda")
+    occ = torch.empty((inst.n_edges, n_bins), dtype=torch.int64, device="cuda")
+    off, edges, dep, ttd = d(inst.route_off), d(inst.route_edges), d(inst.depart_step), d(tt)
+    rc = lib.lpsim_surrogate_load(vp(off), vp(edges), vp(dep), inst.n_trips, vp(ttd), inst.n_edges, n_bins,
+                                  bin_steps, horizon, vp(inflow), vp(occ), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(inflow.cpu().numpy(), inflow_ref)
+    assert np.array_equal(occ.cpu().numpy(), occ_ref)
+
+
+def test_features_targets_tt(torch):
+    case("surrogate features, targets, travel-time update")
+    from paper_2406_08496_amd.lpsim import load_library
+
+    lib = load_library()
+    rng = np.random.default_rng(3)
+    E, B, bs = 700, 24, 600
+    inflow = rng.integers(0, 200, size=(E, B)).astype(np.int32)
+    occ = rng.integers(0, 10 ** 6, size=(E, B)).astype(np.int64)
+    length = rng.integers(20, 2000, size=E).astype(np.float32)
+    lanes = rng.integers(1, 5, size=E).astype(np.uint8)
+    speed = rng.choice([13.4, 17.9, 22.4], size=E).astype(np.float32)
+    exits = rng.integers(0, 50, size=(E, B)).astype(np.int32)
+    ttsum = (exits * rng.uniform(5, 400, size=(E, B))).astype(np.int64)
+    tt_free = np.ceil(np.ceil(length) / (speed * 0.5)).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nw = B // 12
+    x = torch.empty((E * nw, 32), dtype=torch.bfloat16, device="cuda")
+    assert lib.lpsim_surrogate_features(E, B, bs, ctypes.c_float(7.0), vp(d(inflow)), vp(d(occ)), vp(d(length)),
+                                        vp(d(lanes)), vp(d(speed)), vp(x), None) == 0
+    y = torch.empty((E * nw, 16), dtype=torch.float32, device="cuda")
+    m = torch.empty((E * nw, 16), dtype=torch.uint8, device="cuda")
+    assert lib.lpsim_surrogate_targets(E, B, vp(d(exits)), vp(d(ttsum)), vp(d(tt_free)), vp(y), vp(m), None) == 0
+    tt = rng.uniform(1, 300, size=(E, B)).astype(np.float32)
+    ttd = d(tt)
+    yp = rng.normal(scale=0.5, size=(E * nw, 16)).astype(np.float32)
+    assert lib.lpsim_surrogate_tt(E, B, vp(d(yp)), vp(d(tt_free)), ctypes.c_float(0.5), ctypes.c_float(5000.0),
+                                  vp(ttd), None) == 0
+    torch.cuda.synchronize()
+    xf = oa.features(inflow, occ, length, lanes, speed, bs, 7.0)
+    xg = mlp.from_bits(x.view(torch.int16).cpu().numpy().view(np.uint16))
+    assert np.all(np.abs(xg - xf) <= 2.0 ** -7 * np.abs(xf) + 1e-30)
+    yr, mr = oa.targets(exits, ttsum, tt_free.astype(np.float64))
+    assert np.array_equal(m.cpu().numpy().astype(bool), mr)
+    assert np.allclose(y.cpu().numpy(), yr, rtol=1e-5, atol=2e-6)
+    tr = oa.tt_update(tt, yp.astype(np.float64), tt_free.astype(np.float64), 0.5, 5000.0)
+    assert np.allclose(ttd.cpu().numpy(), tr, rtol=2e-6)
+
+
+def test_msa_small_end_to_end(torch):
+    case("MSA, 6 iterations, plain vs surrogate, 8x8 grid")
+    from paper_2406_08496_amd.assign import Assignment, agreement
+
+    inst = synth.grid_instance(seed=13, side=8, n_trips=3000, depart_window=1200, len_lo=100, len_hi=300)
+    inst.n_steps = 4800
+    a = Assignment(inst, n_bins=24)
+    plain = a.run_plain(6)
+    b = Assignment(inst, n_bins=24)
+    sur = b.run_surrogate(6, judge_every=3, tol=10.0, train_steps=50, batch=2048)
+    modes = [h["mode"] for h in sur["hist"]]
+    assert modes[0] == "sim" and "surrogate" in modes
+    for res in (plain, sur):
+        off, edges = res["routes"]
+        assert off[-1] == len(edges)
+        for i in range(0, inst.n_trips, 97):
+            r = edges[off[i]:off[i + 1]]
+            assert inst.src[r[0]] == inst.meta["origin"][i] and inst.dst[r[-1]] == inst.meta["dest"][i]
+            assert np.all(inst.dst[r[:-1]] == inst.src[r[1:]])
+    g = agreement(sur["tt"], plain["tt"], plain["exits"])
+    assert np.isfinite(g)

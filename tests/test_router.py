@@ -1,0 +1,100 @@
+"""The assignment loop's shortest-time router (host code in the library):
+route costs equal Dijkstra distances from an independent library routine,
+routes are contiguous and end at their destination, ties go to the lower
+edge id, and old routes are kept where asked."""
+import ctypes
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import dijkstra
+
+from paper_2406_08496_amd import synth
+from paper_2406_08496_amd.assign import Router
+from paper_2406_08496_amd.lpsim import LpsimError
+
+
+def check_routes(inst, cost, origin, dest, off, edges):
+    n = inst.n_nodes
+    # shortest distance to each destination (reverse graph), independent routine
+    g = csr_matrix((cost, (inst.dst, inst.src)), shape=(n, n))
+    # parallel edges: keep the cheaper one (csr would sum duplicates)
+    order = np.lexsort((cost, inst.dst, inst.src))
+    key = inst.src[order].astype(np.int64) * n + inst.dst[order]
+    first = np.ones(len(order), bool)
+    first[1:] = key[1:] != key[:-1]
+    o = order[first]
+    g = csr_matrix((cost[o], (inst.dst[o], inst.src[o])), shape=(n, n))
+    dests = np.unique(dest)
+    dist = dijkstra(g, indices=dests)
+    di = np.searchsorted(dests, dest)
+    for i in range(len(origin)):
+        r = edges[off[i]:off[i + 1]]
+        assert len(r) > 0
+        assert inst.src[r[0]] == origin[i] and inst.dst[r[-1]] == dest[i]
+        assert np.all(inst.dst[r[:-1]] == inst.src[r[1:]])
+        assert abs(cost[r].sum() - dist[di[i], origin[i]]) <= 1e-9 * max(1.0, dist[di[i], origin[i]])
+
+
+def test_routes_are_shortest_on_grid():
+    inst = synth.grid_instance(seed=4, side=7, n_trips=300)
+    rng = np.random.default_rng(0)
+    cost = (inst.length / inst.speed).astype(np.float64) * rng.uniform(0.5, 3.0, size=inst.n_edges)
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=4)
+    off, edges = r.routes(cost, o, d)
+    check_routes(inst, cost, o, d, off, edges)
+
+
+def test_routes_match_generator_free_flow():
+    """With free-flow costs the router reproduces the generator's routes
+    (both take ties to the lower edge id)."""
+    inst = synth.regional(0.003)
+    cost = inst.length.astype(np.float64) / inst.speed.astype(np.float64)
+    r = Router(inst.n_nodes, inst.src, inst.dst)
+    off, edges = r.routes(cost, inst.meta["origin"], inst.meta["dest"])
+    assert np.array_equal(off, inst.route_off) and np.array_equal(edges, inst.route_edges)
+
+
+def test_ties_go_to_lower_edge_id():
+    # two parallel two-edge paths 0->1->3 and 0->2->3 with equal cost
+    src = np.array([0, 1, 0, 2], np.int32)
+    dst = np.array([2, 3, 1, 3], np.int32)
+    cost = np.ones(4)
+    r = Router(4, src, dst, n_threads=1)
+    off, edges = r.routes(cost, np.array([0], np.int32), np.array([3], np.int32))
+    # path via node 2 uses edges 0 then 3; via node 1 uses 2 then 1: first edge 0 < 2
+    assert list(edges) == [0, 3]
+
+
+def test_keep_old_routes_and_errors():
+    inst = synth.grid_instance(seed=5, side=5, n_trips=50)
+    cost = (inst.length / inst.speed).astype(np.float64) * 2.0
+    cost[inst.route_edges[:3]] *= 10.0
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    r = Router(inst.n_nodes, inst.src, inst.dst)
+    take = np.zeros(50, np.uint8)
+    take[::2] = 1
+    off, edges = r.routes(cost, o, d, old=(inst.route_off, inst.route_edges), take_new=take)
+    for i in range(1, 50, 2):
+        assert np.array_equal(edges[off[i]:off[i + 1]], inst.route(i))
+    with pytest.raises(LpsimError):
+        r.routes(-cost, o, d)
+    with pytest.raises(LpsimError):
+        r.routes(cost, o, o)
+
+
+def test_msa_switch_share():
+    """The deterministic switch picks about 1/(n+1) of the trips (binomial
+    tolerance) and differs between iterations."""
+    from paper_2406_08496_amd.assign import msa_switch
+
+    N = 200_000
+    prev = None
+    for n in (1, 2, 5, 29):
+        s = msa_switch(N, n, 0xA55)
+        p = 1.0 / (n + 1)
+        assert abs(s.mean() - p) <= 5 * np.sqrt(p * (1 - p) / N)
+        if prev is not None:
+            assert not np.array_equal(s, prev)
+        prev = s
