@@ -30,10 +30,34 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the move kernel per active vehicle-step, besides the
-# measured lane-map / next-edge bytes (scan_bytes counter):
-#   slot state read: x, v, edge, meta (16) + edge record (16)
+# lane-map cells it scans and the next edge's flags and entry window (counted
+# on the device into scan_bytes, one byte per cell):
+#   slot state read: meta, x, v, trip id, next edge (20) + the cached edge data
+#     the update needs: lane offset, cells | look-ahead, speed limit, next
+#     lane offset (16)
 #   slot state write: x, v, meta (12)
-MOVE_FIXED_BYTES = 16 + 16 + 12
+MOVE_FIXED_BYTES = 20 + 16 + 12
+
+# HBM traffic of one k_move launch on this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean over the 28,800
+# launches), each scaled by what the same counter reads for a plain 1 GiB
+# device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
+# Valid only for the kernel source it was taken on (sha256 below); otherwise
+# the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
+MOVE_TRAFFIC = {"kernels_sha256": None, "fetch_kib": None, "write_kib": None,
+                "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def move_traffic_bytes():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    t = MOVE_TRAFFIC
+    if t["kernels_sha256"] != sha or t["fetch_kib"] is None:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
 
 def log(*a):
@@ -88,6 +112,8 @@ def main():
     ap.add_argument("--assign", type=int, default=0,
                     help="also run N MSA iterations, plain vs surrogate (regional workload)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape first")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), to scale the HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -100,6 +126,15 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}), flush=True)
+        return
     t = time.perf_counter()
     inst, n_bins = make_workload(args.workload)
     batch = isinstance(inst, list)
@@ -160,7 +195,7 @@ def main():
         f"arrived {c['arrived']}/{n_trips}, active {c['active']}, watchdog {c['watchdog']}")
 
     out = {
-        "metric": "vehicle-steps/sec at 2.8M trips",
+        "metric": "vehicle-steps/sec at 2.8M trips" if not batch else "vehicle-steps/sec, batched scenarios",
         "value": value,
         "unit": "vehicle-steps/s",
         "n_gpus": 1,
@@ -197,7 +232,7 @@ def main():
         achieved = alg_bytes / (mv_ms / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": "k_move", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": None,
+                           "traffic": move_traffic_bytes(),
                            "bytes_per_launch": alg_bytes / max(mv_n, 1),
                            "avg_launch_us": mv_ms * 1e3 / max(mv_n, 1)}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],

@@ -224,10 +224,13 @@ int32_t lpsim_autotune(lpsim_ctx *ctx, int32_t n_steps, const int32_t *block_siz
                        double *trial_us);
 
 /* Kernel timing for measurement: when on, lpsim_step launches kernels one by
- * one and records a HIP event pair around each on the work stream;
- * lpsim_kernel_times then returns the summed milliseconds and launch counts
- * of the phases (0 move, 1 departure requests, 2 resolve, 3 departures,
- * 4 lane change, 5 commit and end of step, 6 reorder).
+ * one on the work stream, each with a HIP event pair that takes the
+ * dispatch's own start and end timestamps (hipExtLaunchKernel), so a phase's
+ * time is its kernel's execution time; the reorder (several kernels) has an
+ * event pair recorded around it.  lpsim_kernel_times then returns the summed
+ * milliseconds and launch counts of the phases (0 move, 1 departure
+ * requests, 2 resolve, 3 departures, 4 lane change, 5 lane-change commit,
+ * 6 reorder, 7 end of step).
  * Turning it on or off resets the sums. */
 int32_t lpsim_set_timing(lpsim_ctx *ctx, int32_t on);
 int32_t lpsim_kernel_times(lpsim_ctx *ctx, double *ms_out, int64_t *launches_out,
@@ -352,6 +355,23 @@ int32_t lpsim_surrogate_targets(int32_t n_edges, int32_t n_bins, const int32_t *
  * tt_steps[e][b] <- (1-damping) tt + damping clamp(tt_free exp(y), 1, tt_max). */
 int32_t lpsim_surrogate_tt(int32_t n_edges, int32_t n_bins, const float *y_pred, const float *tt_free_steps,
                            float damping, float tt_max, float *tt_steps, void *stream);
+
+/* Anchored travel-time estimate for new routes (device arrays): the last
+ * simulated travel time of each (edge, bin), anchor_tt_steps [E][B], moved by
+ * the perceptron's predicted change of log travel time between the anchor's
+ * loading and the new loading (y_new, y_anchor: [E * B/12][16] outputs of
+ * lpsim_mlp_forward), the change clamped to [-max_shift, max_shift]:
+ *   tt_steps_out[e][b] = clamp(anchor * exp(dy), 1, tt_max).
+ * Errors: EINVAL (null pointer, bad sizes, max_shift < 0, tt_max < 1). */
+int32_t lpsim_surrogate_shift(int32_t n_edges, int32_t n_bins, const float *y_new, const float *y_anchor,
+                              const float *anchor_tt_steps, float max_shift, float tt_max, float *tt_steps_out,
+                              void *stream);
+
+/* Routing cost per edge in seconds (device arrays; edge_tt_s [E] float64):
+ * the inflow-weighted mean over bins of tt_steps, or tt_free_steps where the
+ * edge has no inflow, at least one step, times dt.  Errors: EINVAL. */
+int32_t lpsim_surrogate_edge_tt(int32_t n_edges, int32_t n_bins, const int32_t *inflow_bin, const float *tt_steps,
+                                const float *tt_free_steps, float dt, double *edge_tt_s, void *stream);
 
 /* Derived constants: 0 -> entry window W (cells), 1 -> look-ahead D (cells)
  * of scenario 0, 2 -> steps per statistics bin. */

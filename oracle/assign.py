@@ -76,3 +76,27 @@ def tt_update(tt, y, tt_free, damping, tt_max):
         p = np.clip(tt_free[:, None] * np.exp(y[rows, :12]), 1.0, tt_max)
         out[:, w * WIN:(w + 1) * WIN] = (1 - damping) * out[:, w * WIN:(w + 1) * WIN] + damping * p
     return out
+
+
+def shift(y_new, y_anchor, anchor_tt, max_shift, tt_max):
+    """Anchored estimate: anchor_tt[e][b] * exp(clamped predicted change of
+    log travel time for the sample (e, b // 12), output b % 12), clamped to
+    [1, tt_max]."""
+    E, B = anchor_tt.shape
+    nw = B // WIN
+    out = np.empty((E, B))
+    for w in range(nw):
+        rows = np.arange(E) * nw + w
+        d = np.clip(y_new[rows, :WIN] - y_anchor[rows, :WIN], -max_shift, max_shift)
+        out[:, w * WIN:(w + 1) * WIN] = np.clip(anchor_tt[:, w * WIN:(w + 1) * WIN] * np.exp(d), 1.0, tt_max)
+    return out
+
+
+def edge_tt(inflow, tt, tt_free, dt):
+    """Routing cost per edge (seconds): entry-weighted mean of the per-bin
+    travel time (steps), free flow where nobody entered, at least one step."""
+    f = inflow.astype(np.float64)
+    den = f.sum(1)
+    num = (f * tt.astype(np.float64)).sum(1)
+    t = np.where(den > 0, num / np.maximum(den, 1.0), tt_free.astype(np.float64))
+    return np.maximum(t, 1.0) * dt

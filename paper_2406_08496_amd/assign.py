@@ -159,113 +159,187 @@ class Assignment:
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
                 "routes": (off, edges)}
 
+    # -- surrogate data path -------------------------------------------------
+    def _surrogate_setup(self):
+        if getattr(self, "_sd", None) is not None:
+            return self._sd
+        torch = self.torch
+        dev = "cuda"
+        inst = self.inst
+        sd = dict(
+            lib=load_library(),
+            stream=ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+            length=torch.from_numpy(inst.length.astype(np.float32)).to(dev),
+            lanes=torch.from_numpy(inst.lanes.astype(np.uint8)).to(dev),
+            speed=torch.from_numpy(inst.speed.astype(np.float32)).to(dev),
+            tt_free=torch.from_numpy(self.tt_free.astype(np.float32)).to(dev),
+            dep=torch.from_numpy(inst.depart_step.astype(np.int32)).to(dev),
+            jam=float(self.sim.params["veh_len"] + self.sim.params["s0"]),
+        )
+        self._sd = sd
+        return sd
+
+    @staticmethod
+    def _vp(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def features(self, inflow_d, occ_d):
+        """Perceptron inputs (bfloat16, [edges * windows, 32]) from binned
+        inflow and occupancy on the device."""
+        sd = self._surrogate_setup()
+        E, B = self.inst.n_edges, self.n_bins
+        x = self.torch.empty((E * (B // WIN), 32), dtype=self.torch.bfloat16, device="cuda")
+        rc = sd["lib"].lpsim_surrogate_features(E, B, self.bin_steps, ctypes.c_float(sd["jam"]), self._vp(inflow_d),
+                                                self._vp(occ_d), self._vp(sd["length"]), self._vp(sd["lanes"]),
+                                                self._vp(sd["speed"]), self._vp(x), sd["stream"])
+        if rc:
+            raise LpsimError(rc, "features")
+        return x
+
+    def samples(self, st):
+        """Training samples from simulator statistics: features x, targets
+        y = log(mean travel time / free-flow time) per bin, mask m of bins
+        with at least one traversal (all device tensors)."""
+        torch = self.torch
+        sd = self._surrogate_setup()
+        E, B = self.inst.n_edges, self.n_bins
+        nw = B // WIN
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        x = self.features(d(st["inflow_bin"]), d(st["occ_bin"]))
+        y = torch.empty((E * nw, 16), dtype=torch.float32, device="cuda")
+        m = torch.empty((E * nw, 16), dtype=torch.uint8, device="cuda")
+        rc = sd["lib"].lpsim_surrogate_targets(E, B, self._vp(d(st["exits_bin"])), self._vp(d(st["tt_bin"])),
+                                               self._vp(sd["tt_free"]), self._vp(y), self._vp(m), sd["stream"])
+        if rc:
+            raise LpsimError(rc, "targets")
+        return x, y, m
+
+    def load(self, off, edges, tt_bins):
+        """Network loading of routes under per-(edge, bin) travel times
+        (device, steps): (inflow, occupancy) on the device."""
+        torch = self.torch
+        sd = self._surrogate_setup()
+        E, B = self.inst.n_edges, self.n_bins
+        vp = self._vp
+        off_d = torch.from_numpy(np.ascontiguousarray(off, np.int64)).to("cuda")
+        edges_d = torch.from_numpy(np.ascontiguousarray(edges, np.int32)).to("cuda")
+        inflow_d = torch.empty((E, B), dtype=torch.int32, device="cuda")
+        occ_d = torch.empty((E, B), dtype=torch.int64, device="cuda")
+        rc = sd["lib"].lpsim_surrogate_load(vp(off_d), vp(edges_d), vp(sd["dep"]), len(self.origin), vp(tt_bins),
+                                            E, B, self.bin_steps, self.horizon, vp(inflow_d), vp(occ_d),
+                                            sd["stream"])
+        if rc:
+            raise LpsimError(rc, "load")
+        return inflow_d, occ_d
+
+    def anchor(self, st, off, edges):
+        """Anchor of the surrogate at a simulation of routes (off, edges):
+        the simulated per-bin travel times and the perceptron inputs of those
+        routes loaded under them."""
+        tt_bins = self.tt_bins_from_stats(st)
+        inflow_d, occ_d = self.load(off, edges, tt_bins)
+        return {"tt_bins": tt_bins, "x": self.features(inflow_d, occ_d)}
+
+    def estimate(self, net, anc, off, edges, max_shift=1.0):
+        """Edge travel times (seconds, host float64) of new routes: load them
+        under the anchor's travel times, let the perceptron predict the change
+        of log travel time against the anchor's own loading, and apply it to
+        the anchor's simulated times (lpsim_surrogate_shift); the routing cost
+        is the entry-weighted mean over bins (lpsim_surrogate_edge_tt)."""
+        torch = self.torch
+        sd = self._surrogate_setup()
+        E, B = self.inst.n_edges, self.n_bins
+        vp = self._vp
+        inflow_d, occ_d = self.load(off, edges, anc["tt_bins"])
+        y_new = net.forward(self.features(inflow_d, occ_d))
+        y_anc = net.forward(anc["x"])
+        tt_new = torch.empty_like(anc["tt_bins"])
+        rc = sd["lib"].lpsim_surrogate_shift(E, B, vp(y_new), vp(y_anc), vp(anc["tt_bins"]),
+                                             ctypes.c_float(max_shift), ctypes.c_float(float(self.horizon)),
+                                             vp(tt_new), sd["stream"])
+        if rc:
+            raise LpsimError(rc, "shift")
+        out = torch.empty(E, dtype=torch.float64, device="cuda")
+        rc = sd["lib"].lpsim_surrogate_edge_tt(E, B, vp(inflow_d), vp(tt_new), vp(sd["tt_free"]),
+                                               ctypes.c_float(self.dt), vp(out), sd["stream"])
+        if rc:
+            raise LpsimError(rc, "edge tt")
+        return out.cpu().numpy()
+
+    def tt_bins_from_stats(self, st):
+        """Per-(edge, bin) mean travel time in steps, free flow where no
+        traversal entered (device, float32)."""
+        ttb = st["tt_bin"] / np.maximum(st["exits_bin"], 1)
+        return self.torch.from_numpy(np.where(st["exits_bin"] > 0, ttb,
+                                              self.tt_free[:, None]).astype(np.float32)).to("cuda")
+
     # -- surrogate-assisted MSA -------------------------------------------------
     def run_surrogate(self, n_iter, judge_every=5, tol=0.05, train_steps=300, batch=8192, lr=2e-3,
-                      passes=3, damping=0.5, mlp_seed=0):
+                      max_shift=1.0, mlp_seed=0, keep_sets=3):
+        """MSA where the perceptron stands in for the simulation between
+        judges.  Every simulated iteration first estimates its own routes
+        with the surrogate (when an anchor exists) and scores that estimate
+        against the simulation: the flow-weighted mean relative error of the
+        edge travel times.  The surrogate evaluates the following iterations
+        only while that error is at most `tol`; a full simulation runs on
+        iterations 1, 1 + judge_every, ... and whenever the last judge
+        failed.  Each simulation re-anchors the surrogate and adds training
+        samples (its own loading features, simulated targets)."""
         from .surrogate import EdgeMLP
 
         torch = self.torch
         dev = "cuda"
-        lib = load_library()
-        E, B = self.inst.n_edges, self.n_bins
-        nw = B // WIN
-        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-        length_d = torch.from_numpy(self.inst.length.astype(np.float32)).to(dev)
-        lanes_d = torch.from_numpy(self.inst.lanes.astype(np.uint8)).to(dev)
-        speed_d = torch.from_numpy(self.inst.speed.astype(np.float32)).to(dev)
-        tt_free_d = torch.from_numpy(self.tt_free.astype(np.float32)).to(dev)
-        dep_d = torch.from_numpy(self.inst.depart_step.astype(np.int32)).to(dev)
-        jam = float(self.sim.params["veh_len"] + self.sim.params["s0"])
         net = EdgeMLP(seed=mlp_seed)
-        vp = lambda t: ctypes.c_void_p(t.data_ptr())
-
-        def check(rc, what):
-            if rc:
-                raise LpsimError(rc, what)
-
-        def features(inflow_d, occ_d):
-            x = torch.empty((E * nw, 32), dtype=torch.bfloat16, device=dev)
-            check(lib.lpsim_surrogate_features(E, B, self.bin_steps, ctypes.c_float(jam), vp(inflow_d), vp(occ_d),
-                                               vp(length_d), vp(lanes_d), vp(speed_d), vp(x), stream), "features")
-            return x
-
         t0 = time.perf_counter()
         off, edges = self.inst.route_off, self.inst.route_edges
         hist = []
-        buf_x, buf_y, buf_m = [], [], []
+        buf = []
         use_sur = False
-        tt_bins = torch.from_numpy(np.repeat(self.tt_free[:, None], B, 1).astype(np.float32)).to(dev)
+        anc = None
         for n in range(1, n_iter + 1):
             judge = (n - 1) % judge_every == 0
-            if judge or not use_sur:
+            if anc is None or judge or not use_sur:
+                rec = {"n": n, "mode": "sim"}
+                est = None
+                if anc is not None:
+                    ts = time.perf_counter()
+                    est = self.estimate(net, anc, off, edges, max_shift)
+                    self._add("surrogate", time.perf_counter() - ts)
                 st = self.simulate(off, edges)
                 tt = self.edge_tt_from_stats(st)
                 ts = time.perf_counter()
-                inflow_d = torch.from_numpy(st["inflow_bin"]).to(dev)
-                occ_d = torch.from_numpy(st["occ_bin"]).to(dev)
-                exits_d = torch.from_numpy(st["exits_bin"]).to(dev)
-                ttb_d = torch.from_numpy(st["tt_bin"]).to(dev)
-                x = features(inflow_d, occ_d)
-                y = torch.empty((E * nw, 16), dtype=torch.float32, device=dev)
-                m = torch.empty((E * nw, 16), dtype=torch.uint8, device=dev)
-                check(lib.lpsim_surrogate_targets(E, B, vp(exits_d), vp(ttb_d), vp(tt_free_d), vp(y), vp(m), stream),
-                      "targets")
-                # judge: flow-weighted mean relative error of the current model
-                # (host, float64)
-                pred = net.forward(x)[:, :WIN].cpu().numpy().astype(np.float64)
-                yh = y[:, :WIN].cpu().numpy().astype(np.float64)
-                mh = m[:, :WIN].cpu().numpy().astype(bool)
-                w = st["exits_bin"].reshape(E * nw, WIN).astype(np.float64)
-                rel = np.abs(np.expm1(pred - yh)) * mh
-                err = float((rel * w).sum() / max(w.sum(), 1.0))
-                # keep samples that carry a target; train on the recent ones
+                if est is not None:
+                    w = st["n_exits"].astype(np.float64)
+                    err = float((w * np.abs(est - tt) / tt).sum() / max(w.sum(), 1.0))
+                    rec["judge_err"] = err
+                    use_sur = err <= tol
+                anc = self.anchor(st, off, edges)
+                _, y, m = self.samples(st)
                 keep = m[:, :WIN].any(dim=1)
-                buf_x.append(x[keep])
-                buf_y.append(y[keep])
-                buf_m.append(m[keep])
-                buf_x, buf_y, buf_m = buf_x[-3:], buf_y[-3:], buf_m[-3:]
-                X = torch.cat(buf_x)
-                Y = torch.cat(buf_y)
-                M = torch.cat(buf_m)
+                buf.append((anc["x"][keep], y[keep], m[keep]))
+                buf = buf[-keep_sets:]
+                X = torch.cat([b[0] for b in buf])
+                Y = torch.cat([b[1] for b in buf])
+                M = torch.cat([b[2] for b in buf])
                 g = torch.Generator(device=dev)
                 g.manual_seed(n)
-                for s in range(train_steps):
+                for _ in range(train_steps):
                     idx = torch.randint(0, X.shape[0], (min(batch, X.shape[0]),), device=dev, generator=g)
                     net.train_step(X[idx].contiguous(), Y[idx].contiguous(), M[idx].contiguous(), lr=lr)
                 torch.cuda.synchronize()
-                use_sur = err <= tol
                 self._add("train", time.perf_counter() - ts)
-                # estimates for the next surrogate passes start from the simulation
-                ttb = st["tt_bin"] / np.maximum(st["exits_bin"], 1)
-                tt_bins = torch.from_numpy(np.where(st["exits_bin"] > 0, ttb,
-                                                    self.tt_free[:, None]).astype(np.float32)).to(dev)
-                hist.append({"n": n, "mode": "sim", "judge_err": err, "samples": int(X.shape[0])})
+                rec["samples"] = int(X.shape[0])
+                hist.append(rec)
             else:
                 ts = time.perf_counter()
-                off_d = torch.from_numpy(off).to(dev)
-                edges_d = torch.from_numpy(edges).to(dev)
-                inflow_d = torch.empty((E, B), dtype=torch.int32, device=dev)
-                occ_d = torch.empty((E, B), dtype=torch.int64, device=dev)
-                for _ in range(passes):
-                    check(lib.lpsim_surrogate_load(vp(off_d), vp(edges_d), vp(dep_d), len(self.origin), vp(tt_bins),
-                                                   E, B, self.bin_steps, self.horizon, vp(inflow_d), vp(occ_d),
-                                                   stream), "load")
-                    x = features(inflow_d, occ_d)
-                    yp = net.forward(x)
-                    check(lib.lpsim_surrogate_tt(E, B, vp(yp), vp(tt_free_d), ctypes.c_float(damping),
-                                                 ctypes.c_float(float(self.horizon)), vp(tt_bins), stream), "tt")
-                fl = inflow_d.cpu().numpy().astype(np.float64)
-                tb = tt_bins.cpu().numpy().astype(np.float64)
-                tot = fl.sum(1)
-                tt_steps = np.where(tot > 0, (fl * tb).sum(1) / np.maximum(tot, 1.0), self.tt_free)
-                tt = np.maximum(tt_steps, 1.0) * self.dt
+                tt = self.estimate(net, anc, off, edges, max_shift)
                 self._add("surrogate", time.perf_counter() - ts)
                 hist.append({"n": n, "mode": "surrogate"})
             off, edges = self.reroute(tt, off, edges, n)
         wall = time.perf_counter() - t0
         st = self.simulate(off, edges)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
-                "routes": (off, edges)}
+                "routes": (off, edges), "n_sim": sum(1 for h in hist if h["mode"] == "sim")}
 
 
 def agreement(tt_a, tt_b, weights):

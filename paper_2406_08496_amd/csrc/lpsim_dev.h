@@ -130,14 +130,19 @@ struct Dev {
     unsigned long long *partial;  // [MAX_BLOCKS][NPART]
 };
 
-void launch_move(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s);
+// optional timing events of one kernel launch (both null: untimed)
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 constexpr int CAND_BLOCKS = 128;    // grid of the departure kernels (1024 threads)
-void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s);
-void launch_end(const Dev &d, int blocks, hipStream_t s);
+void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+void launch_end(const Dev &d, int blocks, hipStream_t s, KernelEvents ev = {});
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s);
 constexpr int SORT_CHUNK = 4096;  // edges per scan block
 

@@ -19,7 +19,7 @@ using namespace lpsim;
 
 namespace {
 
-constexpr int N_PHASES = 7;
+constexpr int N_PHASES = 8;
 constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
 
 }  // namespace
@@ -538,6 +538,7 @@ static void enqueue_step(lpsim_ctx *c, hipStream_t s) {
     launch_depart(c->d, c->blocks, c->threads, s);
     if (c->dp.lane_change) launch_lanechg(c->d, c->blocks, c->threads, s);
     launch_commit(c->d, c->blocks, c->threads, s);
+    launch_end(c->d, c->blocks, s);
 }
 
 static int32_t build_graphs(lpsim_ctx *c) {
@@ -569,18 +570,27 @@ static int32_t harvest_events(lpsim_ctx *c) {
     return LPSIM_OK;
 }
 
-// one kernel launch bracketed by an event pair on the same stream
-static int32_t timed(lpsim_ctx *c, int phase, hipStream_t s,
-                     void (*fn)(const Dev &, int, int, hipStream_t), int blocks) {
+// the next free event pair, for phase `phase`
+static int32_t next_events(lpsim_ctx *c, int phase, KernelEvents &ev) {
     if ((size_t)(c->ev_used + 1) * 2 > c->ev.size()) {
         int32_t rc = harvest_events(c);
         if (rc) return rc;
     }
     const int i = c->ev_used++;
     c->ev_phase[i] = phase;
-    HIPCHK(c, hipEventRecord(c->ev[2 * i], s));
-    fn(c->d, blocks, c->threads, s);
-    HIPCHK(c, hipEventRecord(c->ev[2 * i + 1], s));
+    ev.start = c->ev[2 * i];
+    ev.stop = c->ev[2 * i + 1];
+    return LPSIM_OK;
+}
+
+// one kernel launch whose events take the dispatch's own start and end
+// timestamps (hipExtLaunchKernel): the kernel's execution time
+static int32_t timed(lpsim_ctx *c, int phase, hipStream_t s,
+                     void (*fn)(const Dev &, int, int, hipStream_t, KernelEvents), int blocks) {
+    KernelEvents ev;
+    int32_t rc = next_events(c, phase, ev);
+    if (rc) return rc;
+    fn(c->d, blocks, c->threads, s, ev);
     return LPSIM_OK;
 }
 
@@ -592,13 +602,21 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
         if ((rc = timed(c, 2, s, launch_resolve, c->blocks))) return rc;
         if ((rc = timed(c, 3, s, launch_depart, c->blocks))) return rc;
         if (c->dp.lane_change && (rc = timed(c, 4, s, launch_lanechg, c->blocks))) return rc;
-        if ((rc = timed(c, 5, s, launch_commit, c->blocks))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, 5, s, launch_commit, c->blocks))) return rc;
+        KernelEvents ev;
+        if ((rc = next_events(c, 7, ev))) return rc;
+        launch_end(c->d, c->blocks, s, ev);
     } else {
         enqueue_step(c, s);
     }
     if (++c->direct_since_reorder >= std::max(c->graph_steps, 32)) {
         if (c->timing) {
-            if ((rc = timed(c, 6, s, launch_reorder, c->blocks))) return rc;
+            // several kernels: an event pair recorded around them
+            KernelEvents ev;
+            if ((rc = next_events(c, 6, ev))) return rc;
+            HIPCHK(c, hipEventRecord(ev.start, s));
+            launch_reorder(c->d, c->blocks, c->threads, s);
+            HIPCHK(c, hipEventRecord(ev.stop, s));
         } else {
             launch_reorder(c->d, c->blocks, c->threads, s);
         }

@@ -31,6 +31,8 @@
 // IEEE division, in exactly the order of the method's definition, so results
 // are identical to the CPU oracle bit for bit.
 
+#include <hip/hip_ext.h>
+
 #include "lpsim_dev.h"
 
 namespace lpsim {
@@ -895,28 +897,40 @@ __global__ void k_sort_finish(Dev d) {
 
 // ---------------------------------------------------------------------------
 
-void launch_move(const Dev &d, int blocks, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_move, dim3(blocks), dim3(threads), 0, s, d);
+// launch on stream s; with timing events given, they take the dispatch's own
+// start and end timestamps (the kernel's execution interval)
+#define LPSIM_LAUNCH(kern, grid, block, s, ev, ...)                                                   \
+    do {                                                                                              \
+        if ((ev).start)                                                                               \
+            hipExtLaunchKernelGGL(kern, grid, block, 0, s, (ev).start, (ev).stop, 0, __VA_ARGS__);   \
+        else                                                                                          \
+            hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                                 \
+    } while (0)
+
+void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
+    LPSIM_LAUNCH(k_move, dim3(blocks), dim3(threads), s, ev, d);
 }
-void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s) {
+void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     (void)blocks;
     (void)threads;
-    hipLaunchKernelGGL(k_cand, dim3(CAND_BLOCKS * 4), dim3(256), 0, s, d);
+    LPSIM_LAUNCH(k_cand, dim3(CAND_BLOCKS * 4), dim3(256), s, ev, d);
 }
-void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s) {
+void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     (void)blocks;
     (void)threads;
-    hipLaunchKernelGGL(k_depart, dim3(CAND_BLOCKS), dim3(1024), 0, s, d);
+    LPSIM_LAUNCH(k_depart, dim3(CAND_BLOCKS), dim3(1024), s, ev, d);
 }
-void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_resolve, dim3(blocks), dim3(threads), 0, s, d);
+void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
+    LPSIM_LAUNCH(k_resolve, dim3(blocks), dim3(threads), s, ev, d);
 }
-void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_lanechg, dim3(blocks), dim3(threads), 0, s, d);
+void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
+    LPSIM_LAUNCH(k_lanechg, dim3(blocks), dim3(threads), s, ev, d);
 }
-void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s) {
-    if (d.p.lane_change) hipLaunchKernelGGL(k_commit, dim3(blocks), dim3(threads), 0, s, d);
-    hipLaunchKernelGGL(k_end, dim3(1), dim3(1024), 0, s, d, (uint32_t)blocks);
+void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
+    if (d.p.lane_change) LPSIM_LAUNCH(k_commit, dim3(blocks), dim3(threads), s, ev, d);
+}
+void launch_end(const Dev &d, int blocks, hipStream_t s, KernelEvents ev) {
+    LPSIM_LAUNCH(k_end, dim3(1), dim3(1024), s, ev, d, (uint32_t)blocks);
 }
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s) {
     const uint32_t n_chunks = ((uint32_t)d.n_edges + SORT_CHUNK - 1) / SORT_CHUNK;

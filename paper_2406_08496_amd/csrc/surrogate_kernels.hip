@@ -112,6 +112,41 @@ __global__ void k_tt(int32_t n_edges, int32_t n_bins, const float *y, const floa
     }
 }
 
+// anchored estimate: the last simulated travel time of each (edge, bin),
+// moved by the perceptron's predicted change of log travel time between the
+// anchor loading and the new one (the change clamped to +-max_shift), then
+// clamped to [1, tt_max]
+__global__ void k_shift(int32_t n_edges, int32_t n_bins, const float *y_new, const float *y_anchor,
+                        const float *anchor_tt, float max_shift, float tt_max, float *tt_out) {
+    const int64_t n = (int64_t)n_edges * n_bins;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = (int32_t)(q % n_bins);
+        const int64_t s = (q / n_bins) * (n_bins / WIN) + b / WIN;
+        const int32_t j = b % WIN;
+        float dlt = y_new[s * NY + j] - y_anchor[s * NY + j];
+        dlt = dlt < -max_shift ? -max_shift : (dlt > max_shift ? max_shift : dlt);
+        float t = anchor_tt[q] * expf(dlt);
+        tt_out[q] = t < 1.0f ? 1.0f : (t > tt_max ? tt_max : t);
+    }
+}
+
+// routing cost of an edge in seconds: the entry-weighted mean over bins of
+// the travel time in steps, free flow where nobody entered, at least one step
+__global__ void k_edge_tt(int32_t n_edges, int32_t n_bins, const int32_t *inflow, const float *tt,
+                          const float *tt_free, float dt, double *out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_edges;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double num = 0.0, den = 0.0;
+        for (int32_t b = 0; b < n_bins; ++b) {
+            const double f = (double)inflow[e * n_bins + b];
+            num += f * (double)tt[e * n_bins + b];
+            den += f;
+        }
+        double t = den > 0.0 ? num / den : (double)tt_free[e];
+        out[e] = (t > 1.0 ? t : 1.0) * (double)dt;
+    }
+}
+
 static unsigned grid_for(int64_t n) {
     const int64_t b = (n + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
@@ -171,6 +206,27 @@ int32_t lpsim_surrogate_tt(int32_t n_edges, int32_t n_bins, const float *y_pred,
     const int64_t n = (int64_t)n_edges * (n_bins / WIN);
     hipLaunchKernelGGL(k_tt, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n_edges, n_bins, y_pred,
                        tt_free_steps, damping, tt_max, tt_steps);
+    return hipGetLastError() == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE;
+}
+
+int32_t lpsim_surrogate_shift(int32_t n_edges, int32_t n_bins, const float *y_new, const float *y_anchor,
+                              const float *anchor_tt_steps, float max_shift, float tt_max, float *tt_steps_out,
+                              void *stream) {
+    if (n_edges < 1 || n_bins < WIN || n_bins % WIN || !y_new || !y_anchor || !anchor_tt_steps || !tt_steps_out ||
+        !(max_shift >= 0.0f) || !(tt_max >= 1.0f))
+        return LPSIM_EINVAL;
+    const int64_t n = (int64_t)n_edges * n_bins;
+    hipLaunchKernelGGL(k_shift, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n_edges, n_bins, y_new,
+                       y_anchor, anchor_tt_steps, max_shift, tt_max, tt_steps_out);
+    return hipGetLastError() == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE;
+}
+
+int32_t lpsim_surrogate_edge_tt(int32_t n_edges, int32_t n_bins, const int32_t *inflow_bin, const float *tt_steps,
+                                const float *tt_free_steps, float dt, double *edge_tt_s, void *stream) {
+    if (n_edges < 1 || n_bins < 1 || !inflow_bin || !tt_steps || !tt_free_steps || !edge_tt_s || !(dt > 0.0f))
+        return LPSIM_EINVAL;
+    hipLaunchKernelGGL(k_edge_tt, dim3(grid_for(n_edges)), dim3(256), 0, (hipStream_t)stream, n_edges, n_bins,
+                       inflow_bin, tt_steps, tt_free_steps, dt, edge_tt_s);
     return hipGetLastError() == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE;
 }
 

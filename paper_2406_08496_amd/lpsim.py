@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblpsim.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5
 WAITING, ACTIVE, ARRIVED = 0, 1, 2
-PHASES = ("move", "cand", "resolve", "depart", "lanechange", "commit", "reorder")
+PHASES = ("move", "cand", "resolve", "depart", "lanechange", "commit", "reorder", "end")
 
 _lib = None
 
@@ -83,6 +83,8 @@ SIGNATURES = {
     "lpsim_surrogate_features": ([_i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_targets": ([_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_tt": ([_i32, _i32, _vp, _vp, ctypes.c_float, ctypes.c_float, _vp, _vp], _i32),
+    "lpsim_surrogate_shift": ([_i32, _i32, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, _vp, _vp], _i32),
+    "lpsim_surrogate_edge_tt": ([_i32, _i32, _vp, _vp, _vp, ctypes.c_float, _vp, _vp], _i32),
     "lpsim_mlp_shape": ([_vp, _vp, _vp], _i32),
     "lpsim_mlp_forward": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "lpsim_mlp_loss_grad": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], _i32),

@@ -94,6 +94,38 @@ def test_features_targets_tt(torch):
     assert np.allclose(ttd.cpu().numpy(), tr, rtol=2e-6)
 
 
+def test_shift_and_edge_tt(torch):
+    case("surrogate anchored shift and routing cost")
+    from paper_2406_08496_amd.lpsim import load_library
+
+    lib = load_library()
+    rng = np.random.default_rng(8)
+    E, B = 513, 36
+    nw = B // 12
+    yn = rng.normal(scale=0.8, size=(E * nw, 16)).astype(np.float32)
+    ya = rng.normal(scale=0.8, size=(E * nw, 16)).astype(np.float32)
+    anc = rng.uniform(0.5, 900.0, size=(E, B)).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = torch.empty((E, B), dtype=torch.float32, device="cuda")
+    assert lib.lpsim_surrogate_shift(E, B, vp(d(yn)), vp(d(ya)), vp(d(anc)), ctypes.c_float(1.0),
+                                     ctypes.c_float(1000.0), vp(out), None) == 0
+    inflow = rng.integers(0, 30, size=(E, B)).astype(np.int32)
+    inflow[::7] = 0  # edges nobody enters: free flow
+    tt_free = rng.uniform(0.5, 60.0, size=E).astype(np.float32)
+    et = torch.empty(E, dtype=torch.float64, device="cuda")
+    assert lib.lpsim_surrogate_edge_tt(E, B, vp(d(inflow)), vp(out), vp(d(tt_free)), ctypes.c_float(0.5), vp(et),
+                                       None) == 0
+    torch.cuda.synchronize()
+    ref = oa.shift(yn.astype(np.float64), ya.astype(np.float64), anc.astype(np.float64), 1.0, 1000.0)
+    got = out.cpu().numpy()
+    assert np.allclose(got, ref, rtol=2e-6)
+    assert np.all(got >= 1.0) and np.all(got <= 1000.0)
+    er = oa.edge_tt(inflow, got, tt_free, 0.5)
+    assert np.allclose(et.cpu().numpy(), er, rtol=1e-12)
+    assert lib.lpsim_surrogate_shift(E, 30, vp(d(yn)), vp(d(ya)), vp(d(anc)), ctypes.c_float(1.0),
+                                     ctypes.c_float(1000.0), vp(out), None) != 0
+
+
 def test_msa_small_end_to_end(torch):
     case("MSA, 6 iterations, plain vs surrogate, 8x8 grid")
     from paper_2406_08496_amd.assign import Assignment, agreement
@@ -106,6 +138,7 @@ def test_msa_small_end_to_end(torch):
     sur = b.run_surrogate(6, judge_every=3, tol=10.0, train_steps=50, batch=2048)
     modes = [h["mode"] for h in sur["hist"]]
     assert modes[0] == "sim" and "surrogate" in modes
+    assert sur["n_sim"] < len(plain["hist"])
     for res in (plain, sur):
         off, edges = res["routes"]
         assert off[-1] == len(edges)

@@ -1,0 +1,103 @@
+"""The regional workload at its full size (225,150 nodes, 550,000 edges,
+2.82M trips, 28,800 steps), in the launch configuration the benchmark times.
+
+The oracle cannot run the whole horizon in test time, so the check has two
+parts:
+- the first 2,400 steps (tens of thousands of vehicles on the road) are
+  compared with the oracle element by element, bit for bit;
+- the GPU then runs on alone to the horizon, and properties that hold at any
+  size are checked every 2,400 steps: conservation, at most one vehicle per
+  cell, front-to-front spacing of at least L in a lane, positions inside their
+  edge, monotone positions on an unchanged edge, no watchdog, and at the end
+  the statistics identities.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_08496_amd import synth
+
+from test_gpu_parity import CNT_KEYS, assert_same_counters, assert_same_state, assert_same_stats, case
+
+pytestmark = pytest.mark.gpu
+
+BENCH_LAUNCH = (256, 2048, 32)
+ST_ACTIVE = 1
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_08496_amd.lpsim import Simulator
+
+    return Simulator
+
+
+def check_properties(v, c, inst, C, speed, prev):
+    n = inst.n_trips
+    st = v["status"]
+    act = st == ST_ACTIVE
+    assert c["waiting"] + c["active"] + c["arrived"] == n
+    assert int(act.sum()) == c["active"]
+    assert c["watchdog"] == 0
+    e = v["edge"][act].astype(np.int64)
+    x = v["x"][act].astype(np.float64)
+    assert np.all(x >= 0) and np.all(x < C[e])
+    assert np.all(v["cell"][act] == np.floor(x))
+    # speed is carried over a transfer, so it is bounded by the fastest limit
+    vv = v["v"][act]
+    assert np.all(vv >= 0) and np.all(vv <= speed.max())
+    assert np.all(v["lane"][act] < inst.lanes[e])
+    key = e * 16 + v["lane"][act]
+    order = np.lexsort((x, key))
+    ks, xs = key[order], x[order]
+    same = ks[1:] == ks[:-1]
+    assert np.all(xs[1:][same] - xs[:-1][same] >= 5.0 - 1e-4)
+    arr = st == 2
+    assert np.all(v["arrival_step"][arr] <= c["step"]) and np.all(v["arrival_step"][~arr] == -1)
+    if prev is not None:
+        pe, px = prev
+        both = act & (pe == v["edge"]) & (pe >= 0)
+        assert np.all(v["x"][both] >= px[both])
+    return v["edge"].copy(), v["x"].copy()
+
+
+def test_regional_full_size(Sim):
+    inst = synth.regional()
+    case("regional full size:", inst.n_nodes, "nodes,", inst.n_edges, "edges,", inst.n_trips, "trips")
+    gpu = Sim(n_bins=48)
+    gpu.set_launch(*BENCH_LAUNCH)
+    gpu.load(inst)
+    ref = oracle.OracleSim(n_bins=48).load(inst)
+    for k in (1200, 2400):
+        gpu.step(1200)
+        ref.step(1200)
+        case("compare with the oracle at step", k)
+        assert_same_state(gpu.vehicles(), ref.vehicles(), f"step {k}")
+        assert_same_counters(gpu.counters(), ref.counters(), f"step {k}")
+    assert_same_stats(gpu.edge_stats(), ref.edge_stats(), "step 2400")
+    assert gpu.counters()["active"] > 10_000
+    del ref
+
+    C = np.ceil(inst.length.astype(np.float64)).astype(np.int64)
+    speed = inst.speed.astype(np.float32)
+    prev = None
+    done = 2400
+    while done < inst.n_steps:
+        gpu.step(2400)
+        done += 2400
+        c = gpu.counters()
+        assert c["step"] == done
+        case("properties at step", done, "active", c["active"], "arrived", c["arrived"])
+        prev = check_properties(gpu.vehicles(), c, inst, C, speed, prev)
+    c = gpu.counters()
+    s = gpu.edge_stats()
+    assert s["n_exits"].sum() == c["transfers"] + c["arrived"]
+    assert s["inflow_bin"].sum() == c["transfers"] + c["departures"]
+    assert np.array_equal(s["exits_bin"].sum(1), s["n_exits"])
+    assert np.array_equal(s["tt_bin"].sum(1), s["tt_sum"])
+    assert s["occ_bin"].sum() == c["vehicle_steps"]
+    assert c["arrived"] > 500_000
