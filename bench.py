@@ -29,14 +29,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the move kernel per active vehicle-step, besides the
-# lane-map cells it scans and the next edge's flags and entry window (counted
-# on the device into scan_bytes, one byte per cell):
-#   slot state read: meta, x, v, trip id, next edge (20) + the cached edge data
-#     the update needs: lane offset, cells | look-ahead, speed limit, next
+# Algorithmic bytes of the move launch per active vehicle-step, besides what
+# the device counts into scan_bytes (lane-map cells scanned, one byte each;
+# the next edge's entry window near the stop line; a crossing vehicle's trip
+# id, claim word and request, 20; the departure requests' queue, trip and
+# entry-window reads, which run in the same launch):
+#   slot state read: meta, x, v (12) + the cached edge data the update needs:
+#     lane offset, cells | look-ahead | next-edge-blocked, speed limit, next
 #     lane offset (16)
 #   slot state write: x, v, meta (12)
-MOVE_FIXED_BYTES = 20 + 16 + 12
+MOVE_FIXED_BYTES = 12 + 16 + 12
 
 # HBM traffic of one k_move launch on this workload, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean over the 28,800
@@ -44,8 +46,8 @@ MOVE_FIXED_BYTES = 20 + 16 + 12
 # device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
 # Valid only for the kernel source it was taken on (sha256 below); otherwise
 # the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
-MOVE_TRAFFIC = {"kernels_sha256": None, "fetch_kib": None, "write_kib": None,
-                "fetch_scale": 2.0, "write_scale": 1.0}
+MOVE_TRAFFIC = {"kernels_sha256": "7e3ccf435593b11acf5b39f7ab81ce374f7caec2fc8af1a2a2ad758813a688f4",
+                "fetch_kib": 33193.05, "write_kib": 17459.94, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def move_traffic_bytes():

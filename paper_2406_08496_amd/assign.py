@@ -204,12 +204,16 @@ class Assignment:
         sd = self._surrogate_setup()
         E, B = self.inst.n_edges, self.n_bins
         nw = B // WIN
+        # device copies held in locals until the kernels have been enqueued
+        # (a temporary freed early would let the next copy reuse its memory)
         d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-        x = self.features(d(st["inflow_bin"]), d(st["occ_bin"]))
+        inflow_d, occ_d = d(st["inflow_bin"]), d(st["occ_bin"])
+        exits_d, ttb_d = d(st["exits_bin"]), d(st["tt_bin"])
+        x = self.features(inflow_d, occ_d)
         y = torch.empty((E * nw, 16), dtype=torch.float32, device="cuda")
         m = torch.empty((E * nw, 16), dtype=torch.uint8, device="cuda")
-        rc = sd["lib"].lpsim_surrogate_targets(E, B, self._vp(d(st["exits_bin"])), self._vp(d(st["tt_bin"])),
-                                               self._vp(sd["tt_free"]), self._vp(y), self._vp(m), sd["stream"])
+        rc = sd["lib"].lpsim_surrogate_targets(E, B, self._vp(exits_d), self._vp(ttb_d), self._vp(sd["tt_free"]),
+                                               self._vp(y), self._vp(m), sd["stream"])
         if rc:
             raise LpsimError(rc, "targets")
         return x, y, m

@@ -73,13 +73,14 @@ struct Slots {
     // per-vehicle copies of what the move phase needs, refreshed when the
     // vehicle enters an edge or changes lane (saves dependent loads)
     uint32_t *lb;   // lane-map offset of the vehicle's lane
-    uint32_t *cd;   // cells | look-ahead << 16 of the current edge
+    uint32_t *cd;   // cells | look-ahead << 16 of the current edge | CD_NEXT_BLOCKED
     float *v0;      // speed limit of the current edge
     uint32_t *tlb;  // lane-map offset of the entry lane on the next edge (NO_NEXT on the last edge)
     uint32_t *tgt;  // claim word of that entry lane
 };
 
 constexpr uint32_t NO_NEXT = 0xffffffffu;
+constexpr uint32_t CD_NEXT_BLOCKED = 1u << 31;  // the next edge accepts no entries
 
 struct Dev {
     Params p;
@@ -127,7 +128,7 @@ struct Dev {
     unsigned long long *tt_sum;
     int32_t *inflow_bin, *exits_bin;
     unsigned long long *tt_bin, *occ_bin;
-    unsigned long long *partial;  // [MAX_BLOCKS][NPART]
+    unsigned long long *partial;  // [PART_ROWS][NPART]
 };
 
 // optional timing events of one kernel launch (both null: untimed)
@@ -135,10 +136,25 @@ struct KernelEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// The move and resolve launches carry the departure work in helper blocks
+// placed before their `blocks` work blocks: enough threads for one pass over
+// DEP_THREADS candidates, a multiple of 8 blocks (so the work blocks keep
+// their XCD placement), at most MAX_HELPERS.
+constexpr uint32_t DEP_THREADS = 131072;
+constexpr uint32_t MAX_HELPERS = 2048;
+inline uint32_t helper_blocks(int threads) {
+    uint32_t x = (DEP_THREADS + (uint32_t)threads - 1) / (uint32_t)threads;
+    x = (x + 7u) & ~7u;
+    return x < MAX_HELPERS ? x : MAX_HELPERS;
+}
+// rows of per-block counters: work blocks, then helper blocks
+constexpr int PART_ROWS = MAX_BLOCKS + (int)MAX_HELPERS;
+
+// refresh the cached blocked flag of vehicles heading for (internal) `edge`
+void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s);
+// move (with departure requests in helper blocks)
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
-void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
-void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
-constexpr int CAND_BLOCKS = 128;    // grid of the departure kernels (1024 threads)
+// resolve (with departures in helper blocks)
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});

@@ -19,7 +19,7 @@ using namespace lpsim;
 
 namespace {
 
-constexpr int N_PHASES = 8;
+constexpr int N_PHASES = 6;
 constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
 
 }  // namespace
@@ -324,7 +324,7 @@ static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
     if ((rc = alloc_n(c, d.exits_bin, nb, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.tt_bin, nb, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.occ_bin, nb, c->net_allocs))) return rc;
-    if ((rc = alloc_n(c, d.partial, (size_t)MAX_BLOCKS * NPART, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.partial, (size_t)PART_ROWS * NPART, c->net_allocs))) return rc;
     const size_t n_chunks = ((size_t)E + SORT_CHUNK - 1) / SORT_CHUNK;
     if ((rc = alloc_n(c, d.ecnt, (size_t)E, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.eoff, (size_t)E, c->net_allocs))) return rc;
@@ -358,7 +358,7 @@ static int32_t reset_run_state(lpsim_ctx *c) {
     HIPCHK(c, hipMemset(d.exits_bin, 0, nb * 4));
     HIPCHK(c, hipMemset(d.tt_bin, 0, nb * 8));
     HIPCHK(c, hipMemset(d.occ_bin, 0, nb * 8));
-    HIPCHK(c, hipMemset(d.partial, 0, (size_t)MAX_BLOCKS * NPART * 8));
+    HIPCHK(c, hipMemset(d.partial, 0, (size_t)PART_ROWS * NPART * 8));
     HIPCHK(c, hipMemset(d.status, 0, N + 1));
     HIPCHK(c, hipMemset(d.arrival, 0xff, (N + 1) * 4));
     HIPCHK(c, hipMemset(d.dclaim, 0, N + 1));
@@ -533,9 +533,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
 
 static void enqueue_step(lpsim_ctx *c, hipStream_t s) {
     launch_move(c->d, c->blocks, c->threads, s);
-    launch_cand(c->d, c->blocks, c->threads, s);
     launch_resolve(c->d, c->blocks, c->threads, s);
-    launch_depart(c->d, c->blocks, c->threads, s);
     if (c->dp.lane_change) launch_lanechg(c->d, c->blocks, c->threads, s);
     launch_commit(c->d, c->blocks, c->threads, s);
     launch_end(c->d, c->blocks, s);
@@ -598,13 +596,11 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     int32_t rc;
     if (c->timing) {
         if ((rc = timed(c, 0, s, launch_move, c->blocks))) return rc;
-        if ((rc = timed(c, 1, s, launch_cand, c->blocks))) return rc;
-        if ((rc = timed(c, 2, s, launch_resolve, c->blocks))) return rc;
-        if ((rc = timed(c, 3, s, launch_depart, c->blocks))) return rc;
-        if (c->dp.lane_change && (rc = timed(c, 4, s, launch_lanechg, c->blocks))) return rc;
-        if (c->dp.lane_change && (rc = timed(c, 5, s, launch_commit, c->blocks))) return rc;
+        if ((rc = timed(c, 1, s, launch_resolve, c->blocks))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, 2, s, launch_lanechg, c->blocks))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, 3, s, launch_commit, c->blocks))) return rc;
         KernelEvents ev;
-        if ((rc = next_events(c, 7, ev))) return rc;
+        if ((rc = next_events(c, 5, ev))) return rc;
         launch_end(c->d, c->blocks, s, ev);
     } else {
         enqueue_step(c, s);
@@ -613,7 +609,7 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
         if (c->timing) {
             // several kernels: an event pair recorded around them
             KernelEvents ev;
-            if ((rc = next_events(c, 6, ev))) return rc;
+            if ((rc = next_events(c, 4, ev))) return rc;
             HIPCHK(c, hipEventRecord(ev.start, s));
             launch_reorder(c->d, c->blocks, c->threads, s);
             HIPCHK(c, hipEventRecord(ev.stop, s));
@@ -709,8 +705,10 @@ int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out) {
     }
     c->ev.resize(2 * 512);
     c->ev_phase.resize(512);
+    // timing events without the system-scope fence: they order work on the
+    // device only, so recording them adds as little as possible to a launch
     for (auto &e : c->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             (void)hipGetLastError();
             e = nullptr;
         }
@@ -918,10 +916,10 @@ int32_t lpsim_get_counters(lpsim_ctx *c, lpsim_counters *out) {
     int32_t rc = check_ready(c, true);
     if (rc) return rc;
     if ((rc = sync_all(c))) return rc;
-    std::vector<unsigned long long> part((size_t)MAX_BLOCKS * NPART);
+    std::vector<unsigned long long> part((size_t)PART_ROWS * NPART);
     HIPCHK(c, hipMemcpy(part.data(), c->d.partial, part.size() * 8, hipMemcpyDeviceToHost));
     unsigned long long tot[NPART] = {0};
-    for (size_t b = 0; b < (size_t)MAX_BLOCKS; ++b)
+    for (size_t b = 0; b < (size_t)PART_ROWS; ++b)
         for (int j = 0; j < NPART; ++j) tot[j] += part[b * NPART + j];
     Ctrl ct;
     if ((rc = read_ctrl(c, ct))) return rc;
@@ -950,6 +948,12 @@ int32_t lpsim_block_edge(lpsim_ctx *c, int32_t edge, int32_t on) {
     if (on) c->aux_h[i] |= AUX_BLOCKED;
     else c->aux_h[i] &= ~AUX_BLOCKED;
     HIPCHK(c, hipMemcpy(c->d.aux + i, &c->aux_h[i], 4, hipMemcpyHostToDevice));
+    if (c->have_trips) {
+        // vehicles already heading for this edge carry its flag in their cache
+        launch_set_next_blocked(c->d, i, on != 0, c->own);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(c->own));
+    }
     return LPSIM_OK;
 }
 
@@ -1006,7 +1010,7 @@ struct SnapHeader {
 
 static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_wq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
-    return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)MAX_BLOCKS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
+    return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)PART_ROWS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
            E * 12 + E * B * 24 + (size_t)n_slots * 56 + (size_t)n_wq * 4;
 }
 
@@ -1040,7 +1044,7 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
         p += n;
         return LPSIM_OK;
     };
-    if ((rc = get(d.partial, (size_t)MAX_BLOCKS * NPART * 8))) return rc;
+    if ((rc = get(d.partial, (size_t)PART_ROWS * NPART * 8))) return rc;
     if ((rc = get(d.map, c->map_bytes))) return rc;
     if ((rc = get(d.status, N + 1))) return rc;
     if ((rc = get(d.arrival, (N + 1) * 4))) return rc;
@@ -1092,7 +1096,7 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
         p += n;
         return LPSIM_OK;
     };
-    if ((rc = put(d.partial, (size_t)MAX_BLOCKS * NPART * 8))) return rc;
+    if ((rc = put(d.partial, (size_t)PART_ROWS * NPART * 8))) return rc;
     if ((rc = put(d.map, c->map_bytes))) return rc;
     if ((rc = put(d.status, N + 1))) return rc;
     if ((rc = put(d.arrival, (N + 1) * 4))) return rc;

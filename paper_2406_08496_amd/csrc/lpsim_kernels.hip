@@ -37,20 +37,21 @@
 
 namespace lpsim {
 
-__device__ __forceinline__ uint32_t logical_block() {
-    const uint32_t G = gridDim.x, b = blockIdx.x;
-    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
-    // contiguous eighth of the work list so neighbouring vehicles (which read
-    // neighbouring lane-map bytes) share that XCD's L2.
+// Work block b of G (b counted after any leading helper blocks, whose number
+// is a multiple of 8) -> its share of the work list.  Blocks are dispatched
+// round-robin over the 8 XCDs; give each XCD one contiguous eighth of the
+// list so neighbouring vehicles (which read neighbouring lane-map bytes)
+// share that XCD's L2.
+__device__ __forceinline__ uint32_t logical_block(uint32_t b, uint32_t G) {
     if ((G & 7u) == 0u) return (b & 7u) * (G >> 3) + (b >> 3);
     return b;
 }
 
-__device__ __forceinline__ void block_range(uint64_t total, uint64_t &lo, uint64_t &hi) {
-    const uint64_t G = gridDim.x;
+// [lo, hi) of a list of `total` items for logical block lb of G
+__device__ __forceinline__ void block_range(uint64_t total, uint32_t lb, uint32_t G, uint64_t &lo, uint64_t &hi) {
     uint64_t chunk = (total + G - 1) / G;
     chunk = (chunk + 63) & ~uint64_t(63);
-    lo = (uint64_t)logical_block() * chunk;
+    lo = (uint64_t)lb * chunk;
     hi = lo + chunk;
     if (hi > total) hi = total;
     if (lo > total) lo = total;
@@ -265,11 +266,11 @@ __device__ __forceinline__ void counts_init(BlockCounts *s) {
     __syncthreads();
 }
 
-__device__ __forceinline__ void counts_flush(const Dev &d, BlockCounts *s) {
+__device__ __forceinline__ void counts_flush(const Dev &d, BlockCounts *s, uint32_t row) {
     __syncthreads();
     if (threadIdx.x < NPART) {
         const unsigned int v = s->c[threadIdx.x];
-        if (v) d.partial[(uint64_t)logical_block() * NPART + threadIdx.x] += v;
+        if (v) d.partial[(uint64_t)row * NPART + threadIdx.x] += v;
     }
 }
 
@@ -280,9 +281,10 @@ __device__ __forceinline__ uint32_t candidate(const Dev &d, const Ctrl *ctl, uin
     return q < nwq ? d.wq[ctl->wq_cur][q] : d.dep_order[ctl->dep_done + (q - nwq)];
 }
 
-// exclusive scan of 1024 values, one per thread (16 wavefronts)
-__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, uint32_t &total) {
-    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+// exclusive scan of one value per thread over the block (blockDim.x a
+// multiple of 64, at most 1024); wsum: 32 words of LDS
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint32_t x = v;
     for (int dlt = 1; dlt < 64; dlt <<= 1) {
         const uint32_t t = __shfl_up(x, dlt);
@@ -291,7 +293,7 @@ __device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, 
     if (lane == 63) wsum[w] = x;
     __syncthreads();
     if (threadIdx.x < 16) {
-        uint32_t y = wsum[threadIdx.x];
+        uint32_t y = threadIdx.x < nw ? wsum[threadIdx.x] : 0u;
         for (int dlt = 1; dlt < 16; dlt <<= 1) {
             const uint32_t t = __shfl_up(y, dlt);
             if (threadIdx.x >= (uint32_t)dlt) y += t;
@@ -299,7 +301,7 @@ __device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *wsum, 
         wsum[16 + threadIdx.x] = y;
     }
     __syncthreads();
-    total = wsum[31];
+    total = wsum[16 + nw - 1];
     const uint32_t before = w ? wsum[16 + w - 1] : 0u;
     return before + x - v;
 }
@@ -319,10 +321,11 @@ __device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int3
 __device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t i, const uint4 &E, uint32_t lane,
                                           int32_t en) {
     S.lb[i] = lane_base(E, lane);
-    S.cd[i] = (uint32_t)E_CELLS(E) | ((uint32_t)E_LOOK(E) << 16);
     S.v0[i] = __uint_as_float(E.z);
+    uint32_t cd = (uint32_t)E_CELLS(E) | ((uint32_t)E_LOOK(E) << 16);
     if (en >= 0) {
         const uint4 En = d.edge[en];
+        if (d.aux[en] & AUX_BLOCKED) cd |= CD_NEXT_BLOCKED;
         const uint32_t nle = (uint32_t)E_LANES(En);
         const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
         S.tlb[i] = lane_base(En, ln);
@@ -331,9 +334,49 @@ __device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t
         S.tlb[i] = NO_NEXT;
         S.tgt[i] = 0;
     }
+    S.cd[i] = cd;
 }
 
-__global__ __launch_bounds__(1024) void k_move(Dev d) {
+// ---------------------------------------------------------------------------
+// departure candidates: due trips request their start lane (reads step k)
+
+__device__ __forceinline__ uint32_t n_candidates(const Dev &d, const Ctrl *ctl) {
+    return ctl->n_wq + (dep_hi_of(d, ctl->k) - ctl->dep_done);
+}
+
+// runs in the X leading blocks of the move launch (hb = 0..X-1), beside the
+// move: it reads the same step-k map and only adds claims.  Its bytes (queue
+// entry 4, status 1, start record 16; for a waiting trip also the edge flags
+// 4, the entry window W and the request flag 1) count into row MAX_BLOCKS + hb.
+__device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X) {
+    __shared__ BlockCounts cnt;
+    counts_init(&cnt);
+    const Ctrl *ctl = d.ctrl;
+    const uint32_t nc = n_candidates(d, ctl);
+    const uint32_t W = (uint32_t)d.p.W;
+    uint32_t bytes = 0;
+    for (uint32_t q = hb * blockDim.x + threadIdx.x; q < nc; q += X * blockDim.x) {
+        const uint32_t j = candidate(d, ctl, q);
+        bytes += 4u + 1u;
+        if (d.status[j] != ST_WAIT) continue;
+        const uint4 o = d.orig[j];
+        const bool ok = !(d.aux[o.z] & AUX_BLOCKED) && first_occ(d.map, o.y, 0, (int32_t)W - 1) < 0;
+        d.dclaim[j] = ok ? 1 : 0;
+        if (ok) atomicMin(&d.claims[o.x], j);
+        bytes += 16u + 4u + W + 1u;
+    }
+    if (bytes) atomicAdd(&cnt.c[P_SCAN], bytes);
+    counts_flush(d, &cnt, MAX_BLOCKS + hb);
+}
+
+// launch: X leading helper blocks (departure requests), then G work blocks
+__global__ __launch_bounds__(1024) void k_move(Dev d, uint32_t X) {
+    if (blockIdx.x < X) {
+        cand_part(d, blockIdx.x, X);
+        return;
+    }
+    const uint32_t G = gridDim.x - X;
+    const uint32_t lb = logical_block(blockIdx.x - X, G);
     __shared__ BlockCounts cnt;
     __shared__ uint32_t s_rl, s_lcc;
     if (threadIdx.x == 0) {
@@ -347,7 +390,7 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
     uint64_t lo64, hi64;
-    block_range(n, lo64, hi64);
+    block_range(n, lb, G, lo64, hi64);
     const uint32_t vlo = (uint32_t)lo64, nv = (uint32_t)(hi64 - lo64);
     unsigned int alive = 0, scanned = 0;
     for (uint32_t base = 0; base < nv; base += blockDim.x) {
@@ -359,18 +402,15 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
             // one round of independent, coalesced loads of the vehicle's state
             const uint32_t m = S.m[i];
             const float x = S.x[i], v = S.v[i];
-            const uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i], id = S.id[i];
+            const uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i];
             const float v0 = S.v0[i];
-            const int32_t en = S.en[i];
             if (!(m & M_DEAD)) {
                 ++alive;
                 const uint32_t lane = m & M_LANE;
-                const int32_t C = (int32_t)(cd & 0xffffu), D = (int32_t)(cd >> 16);
+                const int32_t C = (int32_t)(cd & 0xffffu), D = (int32_t)((cd >> 16) & 0xffu);
                 const int32_t c = (int32_t)x;
                 // stop line inside the look-ahead: the next edge's entry matters
                 const bool near = tlb != NO_NEXT && c + D >= C;
-                uint32_t ax_en = 0;
-                if (near) ax_en = d.aux[en];
                 const int32_t top = c + D < C - 1 ? c + D : C - 1;
                 uint32_t vlb = 0;
                 const int32_t cl = first_occ(d.map, lb, c + 1, top, &vlb);
@@ -388,9 +428,9 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
                 } else {
                     bool stop = false;
                     if (near) {
-                        stop = (ax_en & AUX_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
-                        // next edge's flags (4) and entry window
-                        scanned += 4u + (uint32_t)p.W;
+                        // the next edge's entry window (its blocked flag is cached)
+                        stop = (cd & CD_NEXT_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
+                        scanned += (uint32_t)p.W;
                     }
                     if (stop) {
                         const float gap = (float)C - x;
@@ -409,11 +449,15 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
                     if (tlb == NO_NEXT) {
                         kind = K_ARRIVE;
                     } else {
-                        const uint32_t tgt = S.tgt[i];
+                        // entry request: trip id and claim word are read
+                        // only here (8 bytes), request written (8) and the
+                        // claim word updated (4)
+                        const uint32_t tgt = S.tgt[i], id = S.id[i];
                         kind = K_CLAIM;
                         d.scl[i] = tgt;
                         d.sxo[i] = x;
                         atomicMin(&d.claims[tgt], id);
+                        scanned += 20u;
                     }
                 }
                 const int32_t c2 = kind == K_MOVE ? (int32_t)x2 : c;
@@ -439,38 +483,102 @@ __global__ __launch_bounds__(1024) void k_move(Dev d) {
     }
     if (alive) atomicAdd(&cnt.c[P_VSTEPS], alive);
     if (scanned) atomicAdd(&cnt.c[P_SCAN], scanned);
-    counts_flush(d, &cnt);
+    counts_flush(d, &cnt, lb);
     if (threadIdx.x == 0) {
-        d.rl_cnt[logical_block()] = s_rl;
-        d.lcc_cnt[logical_block()] = s_lcc;
+        d.rl_cnt[lb] = s_rl;
+        d.lcc_cnt[lb] = s_lcc;
     }
 }
 
 // ---------------------------------------------------------------------------
-// departure candidates: due trips request their start lane (reads step k)
+// depart: candidates that won their start lane become vehicles, the others
+// wait in the next queue.  Both lists are built with block-wide scans, so a
+// block makes one atomic per list per pass of 4096 candidates.
 
-__device__ __forceinline__ uint32_t n_candidates(const Dev &d, const Ctrl *ctl) {
-    return ctl->n_wq + (dep_hi_of(d, ctl->k) - ctl->dep_done);
-}
-
-__global__ __launch_bounds__(1024) void k_cand(Dev d) {
-    const Ctrl *ctl = d.ctrl;
+// runs in the X leading blocks of the resolve launch (hb = 0..X-1); its
+// counters go to row MAX_BLOCKS + hb
+__device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t X) {
+    __shared__ BlockCounts cnt;
+    __shared__ uint32_t wsum[32];
+    __shared__ uint32_t s_base[2];
+    counts_init(&cnt);
+    Ctrl *ctl = d.ctrl;
+    const int32_t k = ctl->k;
     const uint32_t nc = n_candidates(d, ctl);
-    const uint32_t W = (uint32_t)d.p.W;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nc; q += gridDim.x * blockDim.x) {
-        const uint32_t j = candidate(d, ctl, q);
-        if (d.status[j] != ST_WAIT) continue;
-        const uint4 o = d.orig[j];
-        const bool ok = !(d.aux[o.z] & AUX_BLOCKED) && first_occ(d.map, o.y, 0, (int32_t)W - 1) < 0;
-        d.dclaim[j] = ok ? 1 : 0;
-        if (ok) atomicMin(&d.claims[o.x], j);
+    const uint32_t n = ctl->n_slots;
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    uint32_t *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
+    bool any_dep = false;
+    for (uint32_t pass0 = hb * blockDim.x; pass0 < nc; pass0 += X * blockDim.x) {
+        const uint32_t q = pass0 + threadIdx.x;
+        uint32_t j = 0;
+        bool dep = false, rq = false;
+        uint4 o = make_uint4(0, 0, 0, 0);
+        if (q < nc) {
+            j = candidate(d, ctl, q);
+            if (d.status[j] == ST_WAIT) {
+                o = d.orig[j];
+                if (d.claims[o.x] == j) {
+                    d.claims[o.x] = 0xffffffffu;
+                    dep = true;
+                } else {
+                    if (d.dclaim[j]) atomicAdd(&cnt.c[P_LOST], 1u);
+                    rq = true;
+                }
+            }
+        }
+        uint32_t tot_dep, tot_rq;
+        const uint32_t my_dep = block_scan(dep ? 1u : 0u, wsum, tot_dep);
+        __syncthreads();
+        const uint32_t my_rq = block_scan(rq ? 1u : 0u, wsum, tot_rq);
+        if (threadIdx.x == 0) {
+            s_base[0] = tot_dep ? atomicAdd(&ctl->n_new, tot_dep) : 0u;
+            s_base[1] = tot_rq ? atomicAdd(&ctl->n_wq_next, tot_rq) : 0u;
+        }
+        __syncthreads();
+        if (rq) wq_next[s_base[1] + my_rq] = j;
+        if (dep) {
+            any_dep = true;
+            const uint32_t ns = n + s_base[0] + my_dep;
+            const int32_t e0 = (int32_t)o.z;
+            const uint32_t r0 = o.w;
+            const uint4 E0 = d.edge[e0];
+            const uint32_t l0 = o.x - E0.w;
+            const uint32_t rend = d.route_off[j + 1];
+            const int32_t en0 = r0 + 1 < rend ? (int32_t)d.route[r0 + 1] : -1;
+            const uint32_t req0 = en0 >= 0 ? required_lane(d, en0, E_LANES(E0)) : 0u;
+            d.status[j] = ST_ACTIVE;
+            S.x[ns] = 0.0f;
+            S.v[ns] = 0.0f;
+            S.e[ns] = e0;
+            S.en[ns] = en0;
+            S.m[ns] = l0 | M_ENTERED | (req0 << M_REQ_SHIFT);
+            S.id[ns] = j;
+            S.rp[ns] = r0;
+            S.rend[ns] = rend;
+            S.ent[ns] = k + 1;
+            set_cache(d, S, ns, E0, l0, en0);
+            d.map[o.y] = speed_byte(0.0f);
+            add_entry(d, e0, k + 1);
+            atomicAdd(&cnt.c[P_DEPARTS], 1u);
+        }
+        __syncthreads();
     }
+    if (any_dep) ctl->dep_ev = 1;
+    counts_flush(d, &cnt, MAX_BLOCKS + hb);
 }
 
 // ---------------------------------------------------------------------------
 // resolve: apply entries, losses, arrivals; commit occupancy; statistics
 
-__global__ __launch_bounds__(1024) void k_resolve(Dev d) {
+// launch: X leading helper blocks (departures), then G work blocks
+__global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
+    if (blockIdx.x < X) {
+        depart_part(d, blockIdx.x, X);
+        return;
+    }
+    const uint32_t G = gridDim.x - X;
+    const uint32_t lb = logical_block(blockIdx.x - X, G);
     __shared__ BlockCounts cnt;
     __shared__ unsigned int s_arr, s_ev;
     if (threadIdx.x == 0) {
@@ -483,9 +591,8 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d) {
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     uint64_t lo64, hi64;
-    block_range(n, lo64, hi64);  // same share as this block had in the move phase
+    block_range(n, lb, G, lo64, hi64);  // same share as this block had in the move phase
     const uint32_t vlo = (uint32_t)lo64;
-    const uint32_t lb = logical_block();
     const uint32_t nrl = d.rl_cnt[lb];
     for (uint32_t it = threadIdx.x; it < nrl; it += blockDim.x) {
         const uint4 r = d.rl_list[vlo + it];
@@ -548,87 +655,11 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d) {
             atomicAdd(&cnt.c[P_LOST], 1u);
         }
     }
-    counts_flush(d, &cnt);
+    counts_flush(d, &cnt, lb);
     if (threadIdx.x == 0) {
         d.blk_arr[lb] = s_arr;
         d.blk_ev[lb] = s_ev;
     }
-}
-
-// ---------------------------------------------------------------------------
-// depart: candidates that won their start lane become vehicles, the others
-// wait in the next queue.  Both lists are built with block-wide scans, so a
-// block makes one atomic per list per pass of 4096 candidates.
-
-__global__ __launch_bounds__(1024) void k_depart(Dev d) {
-    __shared__ BlockCounts cnt;
-    __shared__ uint32_t wsum[32];
-    __shared__ uint32_t s_base[2];
-    counts_init(&cnt);
-    Ctrl *ctl = d.ctrl;
-    const int32_t k = ctl->k;
-    const uint32_t nc = n_candidates(d, ctl);
-    const uint32_t n = ctl->n_slots;
-    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    uint32_t *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
-    bool any_dep = false;
-    for (uint32_t pass0 = blockIdx.x * blockDim.x; pass0 < nc; pass0 += gridDim.x * blockDim.x) {
-        const uint32_t q = pass0 + threadIdx.x;
-        uint32_t j = 0;
-        bool dep = false, rq = false;
-        uint4 o = make_uint4(0, 0, 0, 0);
-        if (q < nc) {
-            j = candidate(d, ctl, q);
-            if (d.status[j] == ST_WAIT) {
-                o = d.orig[j];
-                if (d.claims[o.x] == j) {
-                    d.claims[o.x] = 0xffffffffu;
-                    dep = true;
-                } else {
-                    if (d.dclaim[j]) atomicAdd(&cnt.c[P_LOST], 1u);
-                    rq = true;
-                }
-            }
-        }
-        uint32_t tot_dep, tot_rq;
-        const uint32_t my_dep = block_scan_1024(dep ? 1u : 0u, wsum, tot_dep);
-        __syncthreads();
-        const uint32_t my_rq = block_scan_1024(rq ? 1u : 0u, wsum, tot_rq);
-        if (threadIdx.x == 0) {
-            s_base[0] = tot_dep ? atomicAdd(&ctl->n_new, tot_dep) : 0u;
-            s_base[1] = tot_rq ? atomicAdd(&ctl->n_wq_next, tot_rq) : 0u;
-        }
-        __syncthreads();
-        if (rq) wq_next[s_base[1] + my_rq] = j;
-        if (dep) {
-            any_dep = true;
-            const uint32_t ns = n + s_base[0] + my_dep;
-            const int32_t e0 = (int32_t)o.z;
-            const uint32_t r0 = o.w;
-            const uint4 E0 = d.edge[e0];
-            const uint32_t l0 = o.x - E0.w;
-            const uint32_t rend = d.route_off[j + 1];
-            const int32_t en0 = r0 + 1 < rend ? (int32_t)d.route[r0 + 1] : -1;
-            const uint32_t req0 = en0 >= 0 ? required_lane(d, en0, E_LANES(E0)) : 0u;
-            d.status[j] = ST_ACTIVE;
-            S.x[ns] = 0.0f;
-            S.v[ns] = 0.0f;
-            S.e[ns] = e0;
-            S.en[ns] = en0;
-            S.m[ns] = l0 | M_ENTERED | (req0 << M_REQ_SHIFT);
-            S.id[ns] = j;
-            S.rp[ns] = r0;
-            S.rend[ns] = rend;
-            S.ent[ns] = k + 1;
-            set_cache(d, S, ns, E0, l0, en0);
-            d.map[o.y] = speed_byte(0.0f);
-            add_entry(d, e0, k + 1);
-            atomicAdd(&cnt.c[P_DEPARTS], 1u);
-        }
-        __syncthreads();
-    }
-    if (any_dep) ctl->dep_ev = 1;
-    counts_flush(d, &cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,8 +678,8 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
     const Params &p = d.p;
     (void)ncand_dep;
     uint64_t lo, hi;
-    block_range(n, lo, hi);
-    const uint32_t lb = logical_block();
+    const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
+    block_range(n, lb, gridDim.x, lo, hi);
     const uint32_t ncand = d.lcc_cnt[lb];
     for (uint32_t base = 0; base < ncand; base += blockDim.x) {
         const uint32_t it = base + threadIdx.x;
@@ -679,7 +710,7 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             const int32_t lt = lane + dir;
             const int32_t c = (int32_t)x;
             const uint32_t lb = lb0 + (uint32_t)(dir * C);  // lane lt of the same edge
-            const int32_t D = (int32_t)(cd >> 16);
+            const int32_t D = (int32_t)((cd >> 16) & 0xffu);
             uint32_t vtmp = 0;
             const int32_t top = c + D < C - 1 ? c + D : C - 1;
             // the target cell itself, then the lead and lag gaps
@@ -710,7 +741,7 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             atomicAdd(&cnt.c[P_LC_OK], 1u);
         }
     }
-    counts_flush(d, &cnt);
+    counts_flush(d, &cnt, lb);
     if (threadIdx.x == 0) d.lc_cnt[lb] = s_lc;
 }
 
@@ -725,8 +756,9 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d) {
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     (void)ncand_dep;
     uint64_t lo, hi;
-    block_range(n, lo, hi);
-    const uint32_t nlc = d.lc_cnt[logical_block()];
+    const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
+    block_range(n, lb, gridDim.x, lo, hi);
+    const uint32_t nlc = d.lc_cnt[lb];
     for (uint32_t q = threadIdx.x; q < nlc; q += blockDim.x) {
         const uint32_t i = d.lc_list[lo + q];
         const uint32_t m = S.m[i];
@@ -793,7 +825,7 @@ __global__ __launch_bounds__(1024) void k_sort_count(Dev d) {
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     uint64_t lo, hi;
-    block_range(n, lo, hi);
+    block_range(n, logical_block(blockIdx.x, gridDim.x), gridDim.x, lo, hi);
     const uint32_t lane = lane_id();
     for (uint64_t base = lo; base < hi; base += blockDim.x) {
         const uint64_t it = base + threadIdx.x;
@@ -824,7 +856,7 @@ __global__ __launch_bounds__(1024) void k_sort_scan1(Dev d) {
     for (int j = 0; j < 4; ++j) c[j] = (e0 + j < (uint32_t)d.n_edges) ? d.ecnt[e0 + j] : 0u;
     const uint32_t mine = c[0] + c[1] + c[2] + c[3];
     uint32_t total;
-    uint32_t run = block_scan_1024(mine, wsum, total);
+    uint32_t run = block_scan(mine, wsum, total);
     for (int j = 0; j < 4; ++j) {
         if (e0 + j < (uint32_t)d.n_edges) {
             d.eoff[e0 + j] = run;
@@ -844,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_sort_scan2(Dev d, uint32_t n_chunks) {
     for (uint32_t j = 0; j < per; ++j)
         if (b0 + j < n_chunks) mine += d.csum[b0 + j];
     uint32_t total;
-    uint32_t run = block_scan_1024(mine, wsum, total);
+    uint32_t run = block_scan(mine, wsum, total);
     for (uint32_t j = 0; j < per; ++j) {
         if (b0 + j < n_chunks) {
             const uint32_t cj = d.csum[b0 + j];
@@ -862,7 +894,7 @@ __global__ __launch_bounds__(1024) void k_sort_scatter(Dev d) {
     const Slots A = cur ? d.buf[1] : d.buf[0];
     const Slots B = cur ? d.buf[0] : d.buf[1];
     uint64_t lo, hi;
-    block_range(n, lo, hi);
+    block_range(n, logical_block(blockIdx.x, gridDim.x), gridDim.x, lo, hi);
     for (uint64_t it = lo + threadIdx.x; it < hi; it += blockDim.x) {
         const uint32_t i = (uint32_t)it;
         const uint32_t m = A.m[i];
@@ -895,6 +927,22 @@ __global__ void k_sort_finish(Dev d) {
     }
 }
 
+// the cached blocked flag of every live vehicle whose next edge is `edge`
+__global__ __launch_bounds__(1024) void k_set_next_blocked(Dev d, int32_t edge, uint32_t on) {
+    const Ctrl *ctl = d.ctrl;
+    const uint32_t n = ctl->n_slots;
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if ((S.m[i] & M_DEAD) || S.en[i] != edge) continue;
+        const uint32_t cd = S.cd[i];
+        S.cd[i] = on ? (cd | CD_NEXT_BLOCKED) : (cd & ~CD_NEXT_BLOCKED);
+    }
+}
+
+void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_next_blocked, dim3(1024), dim3(256), 0, s, d, edge, on ? 1u : 0u);
+}
+
 // ---------------------------------------------------------------------------
 
 // launch on stream s; with timing events given, they take the dispatch's own
@@ -908,20 +956,12 @@ __global__ void k_sort_finish(Dev d) {
     } while (0)
 
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
-    LPSIM_LAUNCH(k_move, dim3(blocks), dim3(threads), s, ev, d);
-}
-void launch_cand(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
-    (void)blocks;
-    (void)threads;
-    LPSIM_LAUNCH(k_cand, dim3(CAND_BLOCKS * 4), dim3(256), s, ev, d);
-}
-void launch_depart(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
-    (void)blocks;
-    (void)threads;
-    LPSIM_LAUNCH(k_depart, dim3(CAND_BLOCKS), dim3(1024), s, ev, d);
+    const uint32_t X = helper_blocks(threads);
+    LPSIM_LAUNCH(k_move, dim3(X + (uint32_t)blocks), dim3(threads), s, ev, d, X);
 }
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
-    LPSIM_LAUNCH(k_resolve, dim3(blocks), dim3(threads), s, ev, d);
+    const uint32_t X = helper_blocks(threads);
+    LPSIM_LAUNCH(k_resolve, dim3(X + (uint32_t)blocks), dim3(threads), s, ev, d, X);
 }
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     LPSIM_LAUNCH(k_lanechg, dim3(blocks), dim3(threads), s, ev, d);
