@@ -98,9 +98,9 @@ typedef struct {
     int64_t lc_attempts;   /* lane-change draws that succeeded */
     int64_t lc_accepts;    /* lane changes carried out */
     int64_t watchdog;      /* consecutive steps with vehicles but no entry/exit */
-    int64_t scan_bytes;    /* bytes the move launch reads beyond each vehicle's fixed
-                              state: lane-map cells scanned, next-edge flags and entry
-                              windows, and the departure requests' reads */
+    int64_t scan_bytes;    /* bytes the move launch reads beyond each vehicle's
+                              28-byte state: lane-map cells scanned, next-edge entry
+                              windows, entry requests, and the departure requests' reads */
 } lpsim_counters;
 
 /* Create a context.  `p` (host) is copied and validated: every length, time
@@ -232,7 +232,7 @@ int32_t lpsim_autotune(lpsim_ctx *ctx, int32_t n_steps, const int32_t *block_siz
  * event pair recorded around it.  lpsim_kernel_times then returns the summed
  * milliseconds and launch counts of the phases (0 move with the departure
  * requests, 1 resolve with the departures, 2 lane change, 3 lane-change
- * commit, 4 reorder, 5 end of step).
+ * commit with the end of the step, 4 reorder).
  * Turning it on or off resets the sums. */
 int32_t lpsim_set_timing(lpsim_ctx *ctx, int32_t on);
 int32_t lpsim_kernel_times(lpsim_ctx *ctx, double *ms_out, int64_t *launches_out,

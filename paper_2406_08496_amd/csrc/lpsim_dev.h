@@ -84,7 +84,13 @@ constexpr uint32_t CD_NEXT_BLOCKED = 1u << 31;  // the next edge accepts no entr
 
 struct Dev {
     Params p;
+    // Control of step k lives in buffer k & 1: the kernels of the step read
+    // `ctrl`, and the end of the step (in the commit launch) writes the next
+    // step's control into `ctrl_next`, so no kernel reads a control block
+    // while it is being rewritten.  The host launches each step with the
+    // pair for its parity.
     Ctrl *ctrl;
+    Ctrl *ctrl_next;
     Slots buf[2];
     uint32_t *scl;  // claim word of a crossing vehicle (this step)
     float *sxo;     // its position before the move
@@ -157,8 +163,11 @@ void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEve
 // resolve (with departures in helper blocks)
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
+// lane-change commit (if lane changes are on) and the end of the step, in
+// END_HELPERS leading blocks (the first does the work; 8 keeps the work
+// blocks' XCD placement)
+constexpr uint32_t END_HELPERS = 8;
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
-void launch_end(const Dev &d, int blocks, hipStream_t s, KernelEvents ev = {});
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s);
 constexpr int SORT_CHUNK = 4096;  // edges per scan block
 

@@ -19,7 +19,7 @@ using namespace lpsim;
 
 namespace {
 
-constexpr int N_PHASES = 6;
+constexpr int N_PHASES = 5;
 constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
 
 }  // namespace
@@ -56,13 +56,16 @@ struct lpsim_ctx {
     bool have_trips = false;
     uint32_t slot_cap = 0;
 
-    Dev d{};
+    Dev d{};      // device view with the control pair of parity 0
+    int32_t k = 0;  // current step (its parity picks the control buffer)
 
     // launch shape
     int threads = 256;
     int blocks = 2048;
     int graph_steps = 32;
-    hipGraphExec_t g_full = nullptr, g_one = nullptr;
+    // graphs of graph_steps steps (+ reorder) and of one step, by the parity
+    // of the step they start at
+    hipGraphExec_t g_full[2] = {nullptr, nullptr}, g_one[2] = {nullptr, nullptr};
     int direct_since_reorder = 0;
 
     // timing
@@ -123,9 +126,20 @@ static void dev_free_all(lpsim_ctx *c, std::vector<void *> &owner) {
 }
 
 static void drop_graphs(lpsim_ctx *c) {
-    if (c->g_full) (void)hipGraphExecDestroy(c->g_full);
-    if (c->g_one) (void)hipGraphExecDestroy(c->g_one);
-    c->g_full = c->g_one = nullptr;
+    for (int p = 0; p < 2; ++p) {
+        if (c->g_full[p]) (void)hipGraphExecDestroy(c->g_full[p]);
+        if (c->g_one[p]) (void)hipGraphExecDestroy(c->g_one[p]);
+        c->g_full[p] = c->g_one[p] = nullptr;
+    }
+}
+
+// the device view for a step of parity `par`: its control block is buffer
+// par, the next step's is the other one
+static Dev dev_at(const lpsim_ctx *c, int par) {
+    Dev d = c->d;
+    d.ctrl = c->d.ctrl + par;
+    d.ctrl_next = c->d.ctrl + (par ^ 1);
+    return d;
 }
 
 static int32_t sync_all(lpsim_ctx *c) {
@@ -331,7 +345,8 @@ static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
     if ((rc = alloc_n(c, d.csum, n_chunks + 1, c->net_allocs))) return rc;
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)E * 4));
     d.n_edges = E;
-    if ((rc = alloc_n(c, d.ctrl, 1, c->net_allocs))) return rc;
+    if ((rc = alloc_n(c, d.ctrl, 2, c->net_allocs))) return rc;
+    d.ctrl_next = d.ctrl + 1;
     HIPCHK(c, hipMemset(d.map, 0xff, off + 256));
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)slot * 4));
     c->have_net = true;
@@ -367,6 +382,7 @@ static int32_t reset_run_state(lpsim_ctx *c) {
         HIPCHK(c, hipMemset(a, 0, (size_t)MAX_BLOCKS * 4));
     Ctrl ct{};
     HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
+    c->k = 0;
     // the blocked flags survive a reload of trips
     HIPCHK(c, hipMemcpy(d.aux, c->aux_h.data(), c->aux_h.size() * 4, hipMemcpyHostToDevice));
     HIPCHK(c, hipDeviceSynchronize());
@@ -531,27 +547,30 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
 // ---------------------------------------------------------------------------
 // stepping
 
-static void enqueue_step(lpsim_ctx *c, hipStream_t s) {
-    launch_move(c->d, c->blocks, c->threads, s);
-    launch_resolve(c->d, c->blocks, c->threads, s);
-    if (c->dp.lane_change) launch_lanechg(c->d, c->blocks, c->threads, s);
-    launch_commit(c->d, c->blocks, c->threads, s);
-    launch_end(c->d, c->blocks, s);
+// one step whose control block has parity `par`
+static void enqueue_step(lpsim_ctx *c, hipStream_t s, int par) {
+    const Dev d = dev_at(c, par);
+    launch_move(d, c->blocks, c->threads, s);
+    launch_resolve(d, c->blocks, c->threads, s);
+    if (c->dp.lane_change) launch_lanechg(d, c->blocks, c->threads, s);
+    launch_commit(d, c->blocks, c->threads, s);
 }
 
 static int32_t build_graphs(lpsim_ctx *c) {
     drop_graphs(c);
-    for (int which = 0; which < 2; ++which) {
+    for (int which = 0; which < 4; ++which) {
+        const int p0 = which & 1;
+        const bool full = which < 2;
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
-        const int n = which == 0 ? c->graph_steps : 1;
-        for (int t = 0; t < n; ++t) enqueue_step(c, c->own);
-        if (which == 0) launch_reorder(c->d, c->blocks, c->threads, c->own);
+        const int n = full ? c->graph_steps : 1;
+        for (int t = 0; t < n; ++t) enqueue_step(c, c->own, (p0 + t) & 1);
+        if (full) launch_reorder(dev_at(c, (p0 + n) & 1), c->blocks, c->threads, c->own);
         HIPCHK(c, hipStreamEndCapture(c->own, &g));
         hipGraphExec_t ex = nullptr;
         HIPCHK(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
-        (which == 0 ? c->g_full : c->g_one) = ex;
+        (full ? c->g_full : c->g_one)[p0] = ex;
     }
     return LPSIM_OK;
 }
@@ -583,38 +602,38 @@ static int32_t next_events(lpsim_ctx *c, int phase, KernelEvents &ev) {
 
 // one kernel launch whose events take the dispatch's own start and end
 // timestamps (hipExtLaunchKernel): the kernel's execution time
-static int32_t timed(lpsim_ctx *c, int phase, hipStream_t s,
-                     void (*fn)(const Dev &, int, int, hipStream_t, KernelEvents), int blocks) {
+static int32_t timed(lpsim_ctx *c, const Dev &d, int phase, hipStream_t s,
+                     void (*fn)(const Dev &, int, int, hipStream_t, KernelEvents)) {
     KernelEvents ev;
     int32_t rc = next_events(c, phase, ev);
     if (rc) return rc;
-    fn(c->d, blocks, c->threads, s, ev);
+    fn(d, c->blocks, c->threads, s, ev);
     return LPSIM_OK;
 }
 
 static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     int32_t rc;
+    const Dev d = dev_at(c, c->k & 1);
     if (c->timing) {
-        if ((rc = timed(c, 0, s, launch_move, c->blocks))) return rc;
-        if ((rc = timed(c, 1, s, launch_resolve, c->blocks))) return rc;
-        if (c->dp.lane_change && (rc = timed(c, 2, s, launch_lanechg, c->blocks))) return rc;
-        if (c->dp.lane_change && (rc = timed(c, 3, s, launch_commit, c->blocks))) return rc;
-        KernelEvents ev;
-        if ((rc = next_events(c, 5, ev))) return rc;
-        launch_end(c->d, c->blocks, s, ev);
+        if ((rc = timed(c, d, 0, s, launch_move))) return rc;
+        if ((rc = timed(c, d, 1, s, launch_resolve))) return rc;
+        if (c->dp.lane_change && (rc = timed(c, d, 2, s, launch_lanechg))) return rc;
+        if ((rc = timed(c, d, 3, s, launch_commit))) return rc;
     } else {
-        enqueue_step(c, s);
+        enqueue_step(c, s, c->k & 1);
     }
+    ++c->k;
     if (++c->direct_since_reorder >= std::max(c->graph_steps, 32)) {
+        const Dev dn = dev_at(c, c->k & 1);
         if (c->timing) {
             // several kernels: an event pair recorded around them
             KernelEvents ev;
             if ((rc = next_events(c, 4, ev))) return rc;
             HIPCHK(c, hipEventRecord(ev.start, s));
-            launch_reorder(c->d, c->blocks, c->threads, s);
+            launch_reorder(dn, c->blocks, c->threads, s);
             HIPCHK(c, hipEventRecord(ev.stop, s));
         } else {
-            launch_reorder(c->d, c->blocks, c->threads, s);
+            launch_reorder(dn, c->blocks, c->threads, s);
         }
         c->direct_since_reorder = 0;
     }
@@ -632,7 +651,7 @@ struct HostSlots {
 };
 
 static int32_t read_ctrl(lpsim_ctx *c, Ctrl &ct) {
-    HIPCHK(c, hipMemcpy(&ct, c->d.ctrl, sizeof ct, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&ct, c->d.ctrl + (c->k & 1), sizeof ct, hipMemcpyDeviceToHost));
     return LPSIM_OK;
 }
 
@@ -795,13 +814,17 @@ int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
         for (int32_t t = 0; t < n_steps; ++t)
             if ((rc = step_direct(c, s))) return rc;
     } else {
-        if (!c->g_full && (rc = build_graphs(c))) return rc;
+        if (!c->g_full[0] && (rc = build_graphs(c))) return rc;
         int32_t left = n_steps;
         while (left >= c->graph_steps) {
-            HIPCHK(c, hipGraphLaunch(c->g_full, s));
+            HIPCHK(c, hipGraphLaunch(c->g_full[c->k & 1], s));
+            c->k += c->graph_steps;
             left -= c->graph_steps;
         }
-        for (; left > 0; --left) HIPCHK(c, hipGraphLaunch(c->g_one, s));
+        for (; left > 0; --left) {
+            HIPCHK(c, hipGraphLaunch(c->g_one[c->k & 1], s));
+            ++c->k;
+        }
     }
     if (!hip_stream) HIPCHK(c, hipStreamSynchronize(s));
     return LPSIM_OK;
@@ -950,7 +973,7 @@ int32_t lpsim_block_edge(lpsim_ctx *c, int32_t edge, int32_t on) {
     HIPCHK(c, hipMemcpy(c->d.aux + i, &c->aux_h[i], 4, hipMemcpyHostToDevice));
     if (c->have_trips) {
         // vehicles already heading for this edge carry its flag in their cache
-        launch_set_next_blocked(c->d, i, on != 0, c->own);
+        launch_set_next_blocked(dev_at(c, c->k & 1), i, on != 0, c->own);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipStreamSynchronize(c->own));
     }
@@ -1125,7 +1148,8 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(d.wq[0], (size_t)h.n_wq * 4))) return rc;
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
-    HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d.ctrl + (ct.k & 1), &ct, sizeof ct, hipMemcpyHostToDevice));
+    c->k = ct.k;
     HIPCHK(c, hipDeviceSynchronize());
     return LPSIM_OK;
 }

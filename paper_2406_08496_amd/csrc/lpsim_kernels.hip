@@ -369,8 +369,10 @@ __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X)
     counts_flush(d, &cnt, MAX_BLOCKS + hb);
 }
 
-// launch: X leading helper blocks (departure requests), then G work blocks
-__global__ __launch_bounds__(1024) void k_move(Dev d, uint32_t X) {
+// launch: X leading helper blocks (departure requests), then G work blocks.
+// At most 72 VGPRs (7 wavefronts per SIMD, no spills): this kernel is bound
+// by memory latency, so resident wavefronts matter more than registers.
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_move(Dev d, uint32_t X) {
     if (blockIdx.x < X) {
         cand_part(d, blockIdx.x, X);
         return;
@@ -748,7 +750,50 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
 // ---------------------------------------------------------------------------
 // commit: lane changes into the map
 
-__global__ __launch_bounds__(1024) void k_commit(Dev d) {
+// end of step (first helper block of the commit launch): sums the per-block
+// arrival and event flags of the resolve phase over the G work blocks and
+// writes the next step's control block
+__device__ __forceinline__ void end_part(const Dev &d, uint32_t G) {
+    __shared__ uint32_t s_arr, s_ev;
+    if (threadIdx.x == 0) {
+        s_arr = 0;
+        s_ev = 0;
+    }
+    __syncthreads();
+    uint32_t arr = 0, ev = 0;
+    for (uint32_t b = threadIdx.x; b < G; b += blockDim.x) {
+        arr += d.blk_arr[b];
+        ev |= d.blk_ev[b];
+    }
+    if (arr) atomicAdd(&s_arr, arr);
+    if (ev) s_ev = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const Ctrl c = *d.ctrl;
+        Ctrl nx = c;
+        const bool any = s_ev != 0 || c.dep_ev != 0;
+        nx.watchdog = (c.n_alive > 0 && !any) ? c.watchdog + 1 : 0;
+        nx.dep_ev = 0;
+        nx.n_alive = c.n_alive + (int64_t)c.n_new - (int64_t)s_arr;
+        nx.n_slots = c.n_slots + c.n_new;
+        nx.n_new = 0;
+        nx.dep_done = dep_hi_of(d, c.k);
+        nx.wq_cur = c.wq_cur ^ 1u;
+        nx.n_wq = c.n_wq_next;
+        nx.n_wq_next = 0;
+        nx.k = c.k + 1;
+        *d.ctrl_next = nx;
+    }
+}
+
+// launch: X leading helper blocks (the first ends the step), then G_lc work
+// blocks that write the accepted lane changes into the map (G_lc = 0 when
+// lane changes are off); G = work blocks of the step's other kernels
+__global__ __launch_bounds__(1024) void k_commit(Dev d, uint32_t X, uint32_t G) {
+    if (blockIdx.x < X) {
+        if (blockIdx.x == 0) end_part(d, G);
+        return;
+    }
     const Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
@@ -756,8 +801,8 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d) {
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     (void)ncand_dep;
     uint64_t lo, hi;
-    const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
-    block_range(n, lb, gridDim.x, lo, hi);
+    const uint32_t lb = logical_block(blockIdx.x - X, G);
+    block_range(n, lb, G, lo, hi);
     const uint32_t nlc = d.lc_cnt[lb];
     for (uint32_t q = threadIdx.x; q < nlc; q += blockDim.x) {
         const uint32_t i = d.lc_list[lo + q];
@@ -779,41 +824,6 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d) {
             S.tlb[i] = lane_base(En, ln);
             S.tgt[i] = En.w + ln;
         }
-    }
-}
-
-// end of step: one small block sums the per-block arrival and event flags
-// of the resolve phase and advances the clock and the lists
-__global__ __launch_bounds__(1024) void k_end(Dev d, uint32_t n_blocks) {
-    __shared__ uint32_t s_arr, s_ev;
-    if (threadIdx.x == 0) {
-        s_arr = 0;
-        s_ev = 0;
-    }
-    __syncthreads();
-    uint32_t arr = 0, ev = 0;
-    for (uint32_t b = threadIdx.x; b < n_blocks; b += blockDim.x) {
-        arr += d.blk_arr[b];
-        ev |= d.blk_ev[b];
-    }
-    if (arr) atomicAdd(&s_arr, arr);
-    if (ev) s_ev = 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Ctrl *c = d.ctrl;
-        const int32_t k = c->k;
-        const int64_t alive0 = c->n_alive;
-        const bool ev = s_ev != 0 || c->dep_ev != 0;
-        c->watchdog = (alive0 > 0 && !ev) ? c->watchdog + 1 : 0;
-        c->dep_ev = 0;
-        c->n_alive = alive0 + (int64_t)c->n_new - (int64_t)s_arr;
-        c->n_slots += c->n_new;
-        c->n_new = 0;
-        c->dep_done = dep_hi_of(d, k);
-        c->wq_cur ^= 1u;
-        c->n_wq = c->n_wq_next;
-        c->n_wq_next = 0;
-        c->k = k + 1;
     }
 }
 
@@ -967,10 +977,8 @@ void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, Kernel
     LPSIM_LAUNCH(k_lanechg, dim3(blocks), dim3(threads), s, ev, d);
 }
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
-    if (d.p.lane_change) LPSIM_LAUNCH(k_commit, dim3(blocks), dim3(threads), s, ev, d);
-}
-void launch_end(const Dev &d, int blocks, hipStream_t s, KernelEvents ev) {
-    LPSIM_LAUNCH(k_end, dim3(1), dim3(1024), s, ev, d, (uint32_t)blocks);
+    const uint32_t g_lc = d.p.lane_change ? (uint32_t)blocks : 0u;
+    LPSIM_LAUNCH(k_commit, dim3(END_HELPERS + g_lc), dim3(threads), s, ev, d, END_HELPERS, (uint32_t)blocks);
 }
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s) {
     const uint32_t n_chunks = ((uint32_t)d.n_edges + SORT_CHUNK - 1) / SORT_CHUNK;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblpsim.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECAPACITY = 0, -1, -2, -3, -4, -5
 WAITING, ACTIVE, ARRIVED = 0, 1, 2
-PHASES = ("move", "resolve", "lanechange", "commit", "reorder", "end")
+PHASES = ("move", "resolve", "lanechange", "commit", "reorder")
 
 _lib = None
 
