@@ -46,8 +46,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
 # Valid only for the kernel source it was taken on (sha256 below); otherwise
 # the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
-MOVE_TRAFFIC = {"kernels_sha256": "7e3ccf435593b11acf5b39f7ab81ce374f7caec2fc8af1a2a2ad758813a688f4",
-                "fetch_kib": 33193.05, "write_kib": 17459.94, "fetch_scale": 2.0, "write_scale": 1.0}
+MOVE_TRAFFIC = {"kernels_sha256": "94e11f06efcdc54e43dd23a79e7e8698ede99905135558bf3c1d2bf7b5250717",
+                "fetch_kib": 32953.30, "write_kib": 17300.47, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def move_traffic_bytes():
@@ -111,8 +111,8 @@ def main():
     ap.add_argument("--repeat", type=int, default=3,
                     help="timed runs of the same steps from the same state; the median is reported")
     ap.add_argument("--workload", default="regional")
-    ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--blocks", type=int, default=2048)
+    ap.add_argument("--block", type=int, default=512)
+    ap.add_argument("--blocks", type=int, default=640)
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -146,7 +146,7 @@ struct KernelEvents {
 // placed before their `blocks` work blocks: enough threads for one pass over
 // DEP_THREADS candidates, a multiple of 8 blocks (so the work blocks keep
 // their XCD placement), at most MAX_HELPERS.
-constexpr uint32_t DEP_THREADS = 131072;
+constexpr uint32_t DEP_THREADS = 65536;
 constexpr uint32_t MAX_HELPERS = 2048;
 inline uint32_t helper_blocks(int threads) {
     uint32_t x = (DEP_THREADS + (uint32_t)threads - 1) / (uint32_t)threads;

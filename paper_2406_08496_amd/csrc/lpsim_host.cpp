@@ -59,9 +59,10 @@ struct lpsim_ctx {
     Dev d{};      // device view with the control pair of parity 0
     int32_t k = 0;  // current step (its parity picks the control buffer)
 
-    // launch shape
-    int threads = 256;
-    int blocks = 2048;
+    // launch shape: 640 work blocks of 512 threads (plus the helper blocks)
+    // stay resident in one round on 256 CUs at the move kernel's occupancy
+    int threads = 512;
+    int blocks = 640;
     int graph_steps = 32;
     // graphs of graph_steps steps (+ reorder) and of one step, by the parity
     // of the step they start at

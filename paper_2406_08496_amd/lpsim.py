@@ -220,8 +220,8 @@ class Simulator:
     def step(self, n=1, stream=None):
         self._check(load_library().lpsim_step(self._h, int(n), _stream_handle(stream)))
 
-    def autotune(self, n_steps=64, block_sizes=(128, 256, 512, 1024),
-                 block_counts=(512, 1024, 2048, 4096)):
+    def autotune(self, n_steps=64, block_sizes=(256, 512),
+                 block_counts=(512, 640, 768, 1024, 1280, 1536, 2048)):
         """Pick the fastest launch shape on the current state (state unchanged)."""
         bs = np.ascontiguousarray(block_sizes, np.int32)
         bc = np.ascontiguousarray(block_counts, np.int32)

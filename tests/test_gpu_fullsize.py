@@ -21,7 +21,7 @@ from test_gpu_parity import CNT_KEYS, assert_same_counters, assert_same_state, a
 
 pytestmark = pytest.mark.gpu
 
-BENCH_LAUNCH = (256, 2048, 32)
+BENCH_LAUNCH = (512, 640, 32)
 ST_ACTIVE = 1
 
 
