@@ -118,6 +118,7 @@ class Assignment:
         self.origin = inst.meta["origin"]
         self.dest = inst.meta["dest"]
         self.timings = {}
+        self.progress = None  # optional callable(dict) after each iteration
 
     # -- evaluation by simulation -------------------------------------------
     def simulate(self, off, edges):
@@ -137,6 +138,10 @@ class Assignment:
     def _add(self, k, v):
         self.timings[k] = self.timings.get(k, 0.0) + v
 
+    def _progress(self, rec, t0):
+        if self.progress:
+            self.progress(dict(rec, wall_s=round(time.perf_counter() - t0, 2)))
+
     def reroute(self, cost_s, off, edges, n):
         t0 = time.perf_counter()
         take = msa_switch(len(self.origin), n, self.seed)
@@ -153,6 +158,7 @@ class Assignment:
             st = self.simulate(off, edges)
             tt = self.edge_tt_from_stats(st)
             hist.append({"n": n, "mode": "sim", "mean_tt": float(np.average(tt, weights=st["n_exits"] + 1e-9))})
+            self._progress(hist[-1], t0)
             off, edges = self.reroute(tt, off, edges, n)
         wall = time.perf_counter() - t0
         st = self.simulate(off, edges)
@@ -279,7 +285,7 @@ class Assignment:
 
     # -- surrogate-assisted MSA -------------------------------------------------
     def run_surrogate(self, n_iter, judge_every=5, tol=0.05, train_steps=300, batch=8192, lr=2e-3,
-                      max_shift=1.0, mlp_seed=0, keep_sets=3):
+                      max_shift=1.0, mlp_seed=0, keep_sets=3, judge="mean_rel"):
         """MSA where the perceptron stands in for the simulation between
         judges.  Every simulated iteration first estimates its own routes
         with the surrogate (when an anchor exists) and scores that estimate
@@ -300,6 +306,7 @@ class Assignment:
         buf = []
         use_sur = False
         anc = None
+        prev_tt = None
         for n in range(1, n_iter + 1):
             judge = (n - 1) % judge_every == 0
             if anc is None or judge or not use_sur:
@@ -312,11 +319,17 @@ class Assignment:
                 st = self.simulate(off, edges)
                 tt = self.edge_tt_from_stats(st)
                 ts = time.perf_counter()
+                w = st["n_exits"].astype(np.float64)
                 if est is not None:
-                    w = st["n_exits"].astype(np.float64)
-                    err = float((w * np.abs(est - tt) / tt).sum() / max(w.sum(), 1.0))
+                    errs = edge_tt_errors(est, tt, w)
+                    rec["est_mean_rel"], rec["est_rel_l2"] = errs
+                    err = errs[0] if judge == "mean_rel" else errs[1]
                     rec["judge_err"] = err
                     use_sur = err <= tol
+                if prev_tt is not None:
+                    # what reusing the previous simulation would have scored
+                    rec["stale_mean_rel"], rec["stale_rel_l2"] = edge_tt_errors(prev_tt, tt, w)
+                prev_tt = tt
                 anc = self.anchor(st, off, edges)
                 _, y, m = self.samples(st)
                 keep = m[:, :WIN].any(dim=1)
@@ -334,16 +347,26 @@ class Assignment:
                 self._add("train", time.perf_counter() - ts)
                 rec["samples"] = int(X.shape[0])
                 hist.append(rec)
+                self._progress(rec, t0)
             else:
                 ts = time.perf_counter()
                 tt = self.estimate(net, anc, off, edges, max_shift)
                 self._add("surrogate", time.perf_counter() - ts)
                 hist.append({"n": n, "mode": "surrogate"})
+                self._progress(hist[-1], t0)
             off, edges = self.reroute(tt, off, edges, n)
         wall = time.perf_counter() - t0
         st = self.simulate(off, edges)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
                 "routes": (off, edges), "n_sim": sum(1 for h in hist if h["mode"] == "sim")}
+
+
+def edge_tt_errors(est, ref, weights):
+    """(flow-weighted mean |relative error|, flow-weighted relative L2) of
+    edge travel times `est` against `ref`."""
+    w = np.asarray(weights, np.float64)
+    mean_rel = float((w * np.abs(est - ref) / ref).sum() / max(w.sum(), 1.0))
+    return mean_rel, agreement(est, ref, w)
 
 
 def agreement(tt_a, tt_b, weights):
