@@ -94,9 +94,11 @@ struct Dev {
     Slots buf[2];
     uint32_t *scl;  // claim word of a crossing vehicle (this step)
     float *sxo;     // its position before the move
-    // per-step work lists, one segment per block: block b of the vehicle
-    // kernels owns entries [lo_b, lo_b + count[b]) where [lo_b, hi_b) is its
-    // share of the step's work items (so no global counter is contended)
+    // per-step work lists, one segment per move block: move block b owns
+    // entries [lo_b, lo_b + count[b]) where [lo_b, hi_b) is its share of the
+    // slots (so no global counter is contended).  The resolve kernel deals
+    // the concatenated resolve entries out evenly (share_lists); the lane
+    // change and its commit keep the move block's segment.
     uint4 *rl_list;     // vehicles with an entry request, an arrival or a changed map
                         // byte: {slot, lane-map offset of its lane, old | new cell << 16,
                         // new speed byte | step kind << 8}

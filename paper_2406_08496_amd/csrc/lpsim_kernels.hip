@@ -306,6 +306,54 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t *wsum, uint3
     return before + x - v;
 }
 
+// Even shares of the move blocks' work lists.  cnt[0..G) are the lengths of
+// the G list segments (segment s starts at slot s * chunk, where chunk is the
+// move blocks' share); s_pre (LDS, G + 1 words) receives their exclusive
+// prefix, and this logical block lb takes the entries [q0, q1) of the
+// concatenation.  Balances blocks whose lists are long (intersections)
+// against blocks whose lists are empty.
+__device__ __forceinline__ void share_lists(const uint32_t *cnt, uint32_t G, uint32_t lb, uint32_t *s_pre,
+                                            uint32_t *wsum, uint32_t &q0, uint32_t &q1) {
+    const uint32_t per = (G + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t mine = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < G) {
+            const uint32_t c = cnt[b0 + j];
+            s_pre[b0 + j] = c;
+            mine += c;
+        }
+    uint32_t total;
+    uint32_t run = block_scan(mine, wsum, total);
+    for (uint32_t j = 0; j < per; ++j)
+        if (b0 + j < G) {
+            const uint32_t c = s_pre[b0 + j];
+            s_pre[b0 + j] = run;
+            run += c;
+        }
+    if (threadIdx.x == 0) s_pre[G] = total;
+    __syncthreads();
+    q0 = (uint32_t)((uint64_t)total * lb / G);
+    q1 = (uint32_t)((uint64_t)total * (lb + 1) / G);
+}
+
+// segment of entry q (s_pre[0] <= q < s_pre[G]): the largest s with s_pre[s] <= q
+__device__ __forceinline__ uint32_t seg_of(const uint32_t *s_pre, uint32_t G, uint32_t q) {
+    uint32_t lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= q) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// share of the slot list per move block (as block_range)
+__device__ __forceinline__ uint64_t share_chunk(uint64_t total, uint32_t G) {
+    uint64_t chunk = (total + G - 1) / G;
+    return (chunk + 63) & ~uint64_t(63);
+}
+
 // lane required to leave toward edge `en`: the node's out-edges split the
 // lanes of the incoming edge in proportion to their rank
 __device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int32_t lanes_e) {
@@ -592,12 +640,15 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
     const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    uint64_t lo64, hi64;
-    block_range(n, lb, G, lo64, hi64);  // same share as this block had in the move phase
-    const uint32_t vlo = (uint32_t)lo64;
-    const uint32_t nrl = d.rl_cnt[lb];
-    for (uint32_t it = threadIdx.x; it < nrl; it += blockDim.x) {
-        const uint4 r = d.rl_list[vlo + it];
+    // an even share of all move blocks' resolve lists
+    extern __shared__ uint32_t s_pre[];
+    __shared__ uint32_t wsum[32];
+    uint32_t q0, q1;
+    share_lists(d.rl_cnt, G, lb, s_pre, wsum, q0, q1);
+    const uint64_t chunk = share_chunk(n, G);
+    for (uint32_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+        const uint32_t sg = seg_of(s_pre, G, q);
+        const uint4 r = d.rl_list[(uint64_t)sg * chunk + (q - s_pre[sg])];
         const uint32_t kind = r.w >> 8;
         const int32_t oc = (int32_t)(r.z & 0xffffu), nc = (int32_t)(r.z >> 16);
         uint8_t *lp = d.map + r.y;
@@ -957,13 +1008,14 @@ void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s)
 
 // launch on stream s; with timing events given, they take the dispatch's own
 // start and end timestamps (the kernel's execution interval)
-#define LPSIM_LAUNCH(kern, grid, block, s, ev, ...)                                                   \
+#define LPSIM_LAUNCH_SHM(kern, grid, block, shm, s, ev, ...)                                          \
     do {                                                                                              \
         if ((ev).start)                                                                               \
-            hipExtLaunchKernelGGL(kern, grid, block, 0, s, (ev).start, (ev).stop, 0, __VA_ARGS__);   \
+            hipExtLaunchKernelGGL(kern, grid, block, shm, s, (ev).start, (ev).stop, 0, __VA_ARGS__); \
         else                                                                                          \
-            hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                                 \
+            hipLaunchKernelGGL(kern, grid, block, shm, s, __VA_ARGS__);                               \
     } while (0)
+#define LPSIM_LAUNCH(kern, grid, block, s, ev, ...) LPSIM_LAUNCH_SHM(kern, grid, block, 0, s, ev, __VA_ARGS__)
 
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     const uint32_t X = helper_blocks(threads);
@@ -971,7 +1023,8 @@ void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEve
 }
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     const uint32_t X = helper_blocks(threads);
-    LPSIM_LAUNCH(k_resolve, dim3(X + (uint32_t)blocks), dim3(threads), s, ev, d, X);
+    // dynamic LDS: prefix of the G list lengths
+    LPSIM_LAUNCH_SHM(k_resolve, dim3(X + (uint32_t)blocks), dim3(threads), ((size_t)blocks + 1) * 4, s, ev, d, X);
 }
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev) {
     LPSIM_LAUNCH(k_lanechg, dim3(blocks), dim3(threads), s, ev, d);
