@@ -122,8 +122,10 @@ struct Dev {
     uint32_t n_trips;
     uint8_t *status;
     int32_t *arrival;
-    uint8_t *dclaim;
-    uint32_t *wq[2];      // due trips that have not entered yet
+    uint8_t *dclaim;      // [candidate position] the departure request was made this step
+    // due trips that have not entered yet, with their start record:
+    // {claim word of the start lane, its lane-map offset, first edge, trip id}
+    uint4 *wq[2];
     const uint4 *orig;    // per trip: claim word, lane-map offset of the start
                           // lane, first edge, route index of the first edge
     // per-edge counting sort of the slots (locality), every few steps

@@ -20,7 +20,7 @@ using namespace lpsim;
 namespace {
 
 constexpr int N_PHASES = 5;
-constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e31ull;  // "LPSIMSN1"
+constexpr uint64_t SNAP_MAGIC = 0x4c5053494d534e32ull;  // "LPSIMSN2"
 
 }  // namespace
 
@@ -1035,7 +1035,7 @@ struct SnapHeader {
 static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_wq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)PART_ROWS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
-           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (size_t)n_wq * 4;
+           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (size_t)n_wq * 16;
 }
 
 int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
@@ -1094,7 +1094,7 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = get(S.v0, n * 4))) return rc;
     if ((rc = get(S.tlb, n * 4))) return rc;
     if ((rc = get(S.tgt, n * 4))) return rc;
-    if ((rc = get(d.wq[ct.wq_cur], (size_t)ct.n_wq * 4))) return rc;
+    if ((rc = get(d.wq[ct.wq_cur], (size_t)ct.n_wq * 16))) return rc;
     return LPSIM_OK;
 }
 
@@ -1146,7 +1146,7 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(S.v0, n * 4))) return rc;
     if ((rc = put(S.tlb, n * 4))) return rc;
     if ((rc = put(S.tgt, n * 4))) return rc;
-    if ((rc = put(d.wq[0], (size_t)h.n_wq * 4))) return rc;
+    if ((rc = put(d.wq[0], (size_t)h.n_wq * 16))) return rc;
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
     HIPCHK(c, hipMemcpy(d.ctrl + (ct.k & 1), &ct, sizeof ct, hipMemcpyHostToDevice));

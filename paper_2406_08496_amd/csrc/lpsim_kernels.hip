@@ -276,9 +276,15 @@ __device__ __forceinline__ void counts_flush(const Dev &d, BlockCounts *s, uint3
 
 // the trip at position q of this step's departure candidates: the live
 // waiting queue first, then the trips that fall due at this step
-__device__ __forceinline__ uint32_t candidate(const Dev &d, const Ctrl *ctl, uint32_t q) {
+// {claim word, start-lane offset, first edge, trip id}; *fresh is set for a
+// trip that falls due now (its start record read from the trip table)
+__device__ __forceinline__ uint4 candidate(const Dev &d, const Ctrl *ctl, uint32_t q, bool *fresh) {
     const uint32_t nwq = ctl->n_wq;
-    return q < nwq ? d.wq[ctl->wq_cur][q] : d.dep_order[ctl->dep_done + (q - nwq)];
+    *fresh = q >= nwq;
+    if (q < nwq) return d.wq[ctl->wq_cur][q];
+    const uint32_t j = d.dep_order[ctl->dep_done + (q - nwq)];
+    const uint4 o = d.orig[j];
+    return make_uint4(o.x, o.y, o.z, j);
 }
 
 // exclusive scan of one value per thread over the block (blockDim.x a
@@ -394,8 +400,9 @@ __device__ __forceinline__ uint32_t n_candidates(const Dev &d, const Ctrl *ctl) 
 
 // runs in the X leading blocks of the move launch (hb = 0..X-1), beside the
 // move: it reads the same step-k map and only adds claims.  Its bytes (queue
-// entry 4, status 1, start record 16; for a waiting trip also the edge flags
-// 4, the entry window W and the request flag 1) count into row MAX_BLOCKS + hb.
+// entry 16, or for a trip falling due its id 4 and start record 16; the
+// first edge's flags 4, the entry window W, the request flag 1) count into
+// row MAX_BLOCKS + hb.
 __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X) {
     __shared__ BlockCounts cnt;
     counts_init(&cnt);
@@ -404,14 +411,12 @@ __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X)
     const uint32_t W = (uint32_t)d.p.W;
     uint32_t bytes = 0;
     for (uint32_t q = hb * blockDim.x + threadIdx.x; q < nc; q += X * blockDim.x) {
-        const uint32_t j = candidate(d, ctl, q);
-        bytes += 4u + 1u;
-        if (d.status[j] != ST_WAIT) continue;
-        const uint4 o = d.orig[j];
+        bool fresh;
+        const uint4 o = candidate(d, ctl, q, &fresh);
         const bool ok = !(d.aux[o.z] & AUX_BLOCKED) && first_occ(d.map, o.y, 0, (int32_t)W - 1) < 0;
-        d.dclaim[j] = ok ? 1 : 0;
-        if (ok) atomicMin(&d.claims[o.x], j);
-        bytes += 16u + 4u + W + 1u;
+        d.dclaim[q] = ok ? 1 : 0;
+        if (ok) atomicMin(&d.claims[o.x], o.w);
+        bytes += (fresh ? 4u + 16u : 16u) + 4u + W + 1u;
     }
     if (bytes) atomicAdd(&cnt.c[P_SCAN], bytes);
     counts_flush(d, &cnt, MAX_BLOCKS + hb);
@@ -557,24 +562,22 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
     const uint32_t nc = n_candidates(d, ctl);
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    uint32_t *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
+    uint4 *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
     bool any_dep = false;
     for (uint32_t pass0 = hb * blockDim.x; pass0 < nc; pass0 += X * blockDim.x) {
         const uint32_t q = pass0 + threadIdx.x;
-        uint32_t j = 0;
         bool dep = false, rq = false;
         uint4 o = make_uint4(0, 0, 0, 0);
         if (q < nc) {
-            j = candidate(d, ctl, q);
-            if (d.status[j] == ST_WAIT) {
-                o = d.orig[j];
-                if (d.claims[o.x] == j) {
-                    d.claims[o.x] = 0xffffffffu;
-                    dep = true;
-                } else {
-                    if (d.dclaim[j]) atomicAdd(&cnt.c[P_LOST], 1u);
-                    rq = true;
-                }
+            bool fresh;
+            o = candidate(d, ctl, q, &fresh);
+            const uint8_t claimed = d.dclaim[q];
+            if (d.claims[o.x] == o.w) {
+                d.claims[o.x] = 0xffffffffu;
+                dep = true;
+            } else {
+                if (claimed) atomicAdd(&cnt.c[P_LOST], 1u);
+                rq = true;
             }
         }
         uint32_t tot_dep, tot_rq;
@@ -586,12 +589,13 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             s_base[1] = tot_rq ? atomicAdd(&ctl->n_wq_next, tot_rq) : 0u;
         }
         __syncthreads();
-        if (rq) wq_next[s_base[1] + my_rq] = j;
+        if (rq) wq_next[s_base[1] + my_rq] = o;
         if (dep) {
             any_dep = true;
+            const uint32_t j = o.w;
             const uint32_t ns = n + s_base[0] + my_dep;
             const int32_t e0 = (int32_t)o.z;
-            const uint32_t r0 = o.w;
+            const uint32_t r0 = d.route_off[j];
             const uint4 E0 = d.edge[e0];
             const uint32_t l0 = o.x - E0.w;
             const uint32_t rend = d.route_off[j + 1];
