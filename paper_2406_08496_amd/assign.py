@@ -285,7 +285,7 @@ class Assignment:
 
     # -- surrogate-assisted MSA -------------------------------------------------
     def run_surrogate(self, n_iter, judge_every=5, tol=0.05, train_steps=300, batch=8192, lr=2e-3,
-                      max_shift=1.0, mlp_seed=0, keep_sets=3, judge="mean_rel"):
+                      max_shift=1.0, mlp_seed=0, keep_sets=3, judge_metric="mean_rel"):
         """MSA where the perceptron stands in for the simulation between
         judges.  Every simulated iteration first estimates its own routes
         with the surrogate (when an anchor exists) and scores that estimate
@@ -323,7 +323,7 @@ class Assignment:
                 if est is not None:
                     errs = edge_tt_errors(est, tt, w)
                     rec["est_mean_rel"], rec["est_rel_l2"] = errs
-                    err = errs[0] if judge == "mean_rel" else errs[1]
+                    err = errs[0] if judge_metric == "mean_rel" else errs[1]
                     rec["judge_err"] = err
                     use_sur = err <= tol
                 if prev_tt is not None:

@@ -323,18 +323,21 @@ def tiny_grid() -> Instance:
     return grid_instance(seed=1)
 
 
-def regional(scale: float = 1.0) -> Instance:
+def regional(scale: float = 1.0, demand: float = 1.0) -> Instance:
     """Planar regional graph: 475x474 jittered lattice (225,150 nodes), 550,000
     directed edges, 2.82M gravity trips over a two-peak 3 h morning profile,
-    horizon 3 h + 1 h drain.  `scale` < 1 shrinks every size (for tests)."""
+    horizon 3 h + 1 h drain.  `scale` < 1 shrinks every size (for tests);
+    `demand` scales only the number of trips (same network)."""
     if scale == 1.0:
-        return planar_instance(2, 475, 474, 275_000, 2_820_000, name="regional-225k-2.82M")
+        n = int(round(2_820_000 * demand))
+        name = "regional-225k-2.82M" if demand == 1.0 else f"regional-225k-{n / 1e6:.3g}M"
+        return planar_instance(2, 475, 474, 275_000, n, name=name)
     side = max(8, int(round(475 * np.sqrt(scale))))
     nodes = side * side
     return planar_instance(2, side, side, int(nodes * 275_000 / 225_150),
-                           max(10, int(2_820_000 * scale)),
+                           max(10, int(2_820_000 * scale * demand)),
                            zones=(max(2, int(25 * np.sqrt(scale))), max(2, int(20 * np.sqrt(scale)))),
-                           name=f"regional-x{scale}")
+                           name=f"regional-x{scale}" + ("" if demand == 1.0 else f"-d{demand}"))
 
 
 def large(scale: float = 1.0) -> Instance:
