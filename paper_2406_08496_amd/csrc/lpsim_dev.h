@@ -109,6 +109,7 @@ struct Dev {
     uint32_t *blk_ev;   // [MAX_BLOCKS] any entry or exit in the block this step
     const uint4 *edge;
     uint32_t *aux;
+    int32_t n_scen;       // scenarios in this context (1 unless batched)
     const int32_t *escen;
     const uint64_t *scen_seed;
     const uint32_t *scen_tbase;

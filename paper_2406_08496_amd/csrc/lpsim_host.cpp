@@ -330,6 +330,7 @@ static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
     const int32_t *escen_d;
     if ((rc = upload(c, *(int32_t **)&escen_d, escen.data(), escen.size(), c->net_allocs))) return rc;
     d.escen = escen_d;
+    d.n_scen = S;
     if ((rc = alloc_n(c, d.map, off + 256, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.claims, (size_t)slot, c->net_allocs))) return rc;
     const size_t nb = (size_t)E * (size_t)c->dp.n_bins;

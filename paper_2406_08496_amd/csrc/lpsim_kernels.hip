@@ -734,6 +734,14 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
     (void)ncand_dep;
+    // a single scenario's draw seed and trip base, read once beside the control block
+    const bool one_scen = d.n_scen == 1;
+    uint64_t seed0 = 0;
+    uint32_t tbase0 = 0;
+    if (one_scen) {
+        seed0 = d.scen_seed[0];
+        tbase0 = d.scen_tbase[0];
+    }
     uint64_t lo, hi;
     const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
     block_range(n, lb, gridDim.x, lo, hi);
@@ -759,9 +767,15 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             const int32_t dir = req > lane ? 1 : -1;
             if (((k & 1) == 0 && dir > 0) || ((k & 1) == 1 && dir < 0)) break;
             const float prob = 1.0f - dist / p.x0;
-            const int32_t sc = d.escen[e];
-            const uint32_t loc = id - d.scen_tbase[sc];
-            const uint64_t h = mix64(d.scen_seed[sc] ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
+            uint64_t seed = seed0;
+            uint32_t tbase = tbase0;
+            if (!one_scen) {
+                const int32_t sc = d.escen[e];
+                seed = d.scen_seed[sc];
+                tbase = d.scen_tbase[sc];
+            }
+            const uint32_t loc = id - tbase;
+            const uint64_t h = mix64(seed ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
             if (!((float)(h >> 40) < prob * 16777216.0f)) break;
             atomicAdd(&cnt.c[P_LC_TRY], 1u);
             const int32_t lt = lane + dir;
@@ -770,9 +784,10 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             const int32_t D = (int32_t)((cd >> 16) & 0xffu);
             uint32_t vtmp = 0;
             const int32_t top = c + D < C - 1 ? c + D : C - 1;
-            // the target cell itself, then the lead and lag gaps
-            if (first_occ(d.map, lb, c, c) >= 0) break;
-            const int32_t ca = first_occ(d.map, lb, c + 1, top, &vtmp);
+            // one scan from the target cell: occupied target cell -> no
+            // change; else the first occupied cell is the lead; then the lag
+            const int32_t ca = first_occ(d.map, lb, c, top, &vtmp);
+            if (ca == c) break;
             if (ca >= 0) {
                 const float va = (float)vtmp;
                 const float g_lead = ((float)ca - x) - p.L;
