@@ -1,0 +1,73 @@
+"""Host-side logic that needs no GPU: the benchmark's command-line contract,
+its byte model and traffic bookkeeping, and argument checks of the
+surrogate entry points (they validate before touching the device)."""
+import ctypes
+import hashlib
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2406_08496_amd import lpsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in out["error"]
+
+
+def test_bench_byte_model_and_traffic_key():
+    import bench
+
+    # 28 bytes of state read and 12 written per vehicle-step
+    assert bench.MOVE_FIXED_BYTES == 40
+    src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    t = bench.move_traffic_bytes()
+    if bench.MOVE_TRAFFIC["kernels_sha256"] == sha:
+        m = bench.MOVE_TRAFFIC
+        assert t == pytest.approx((m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024)
+    else:
+        assert t is None  # counters were taken on another kernel source
+
+
+def test_bench_workload_names():
+    import bench
+
+    assert bench.make_workload("tiny")[0].n_trips == 2000
+    inst, nb = bench.make_workload("regional:0.002")
+    assert nb == 48 and inst.n_trips > 0
+    inst, _ = bench.make_workload("regional-demand:0.5")
+    assert inst.n_edges == 550_000 and inst.n_trips == 1_410_000
+    with pytest.raises(SystemExit):
+        bench.make_workload("nonsense")
+
+
+def test_surrogate_entry_points_validate_arguments():
+    lib = lpsim.load_library()
+    v = ctypes.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    f = ctypes.c_float
+    assert lib.lpsim_surrogate_features(10, 13, 600, f(7.0), v, v, v, v, v, v, None) == lpsim.EINVAL  # bins % 12
+    assert lib.lpsim_surrogate_features(0, 12, 600, f(7.0), v, v, v, v, v, v, None) == lpsim.EINVAL
+    assert lib.lpsim_surrogate_targets(10, 24, None, v, v, v, v, None) == lpsim.EINVAL
+    assert lib.lpsim_surrogate_tt(10, 24, v, v, f(1.5), f(100.0), v, None) == lpsim.EINVAL  # damping > 1
+    assert lib.lpsim_surrogate_shift(10, 24, v, v, v, f(-1.0), f(100.0), v, None) == lpsim.EINVAL
+    assert lib.lpsim_surrogate_shift(10, 24, v, v, v, f(1.0), f(0.5), v, None) == lpsim.EINVAL
+    assert lib.lpsim_surrogate_edge_tt(10, 24, v, v, v, f(0.0), v, None) == lpsim.EINVAL
+    assert lib.lpsim_surrogate_load(None, None, None, 5, v, 10, 12, 50, 100, v, v, None) == lpsim.EINVAL
+
+
+def test_mlp_entry_points_validate_arguments():
+    lib = lpsim.load_library()
+    i, h, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.lpsim_mlp_shape(ctypes.byref(i), ctypes.byref(h), ctypes.byref(o)) == 0
+    assert (i.value, h.value, o.value) == (32, 256, 16)
+    assert lib.lpsim_mlp_workspace_bytes(8) > 0
