@@ -46,8 +46,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
 # Valid only for the kernel source it was taken on (sha256 below); otherwise
 # the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
-MOVE_TRAFFIC = {"kernels_sha256": "99178b81ff5a18e1fbf6f6f9910ffabdab8536e71f512abe3801a15b4e3720aa",
-                "fetch_kib": 29352.16, "write_kib": 16410.78, "fetch_scale": 2.0, "write_scale": 1.0}
+MOVE_TRAFFIC = {"kernels_sha256": "f1459da57026d07a9792522bf5f74098942226e6bde253fa7d4fd6e5dce9cdb4",
+                "fetch_kib": 29165.33, "write_kib": 16410.81, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def move_traffic_bytes():
