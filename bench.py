@@ -47,7 +47,7 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # Valid only for the kernel source it was taken on (sha256 below); otherwise
 # the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
 MOVE_TRAFFIC = {"kernels_sha256": "f1459da57026d07a9792522bf5f74098942226e6bde253fa7d4fd6e5dce9cdb4",
-                "fetch_kib": 29165.33, "write_kib": 16410.81, "fetch_scale": 2.0, "write_scale": 1.0}
+                "fetch_kib": 29227.16, "write_kib": 16419.04, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def move_traffic_bytes():
@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--workload", default="regional")
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--blocks", type=int, default=640)
-    ap.add_argument("--graph-steps", type=int, default=32)
+    ap.add_argument("--graph-steps", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")

@@ -208,7 +208,8 @@ int32_t lpsim_block_edge(lpsim_ctx *ctx, int32_t edge, int32_t on);
 /* Launch shape: threads per block (64..1024, multiple of 64), blocks per
  * vehicle kernel (multiple of 8, up to 8192), steps captured per HIP graph
  * (>= 1; 0 launches kernels one by one).  Results do not depend on these.
- * Defaults: 512 threads, 640 blocks, 32 steps per graph. */
+ * The slots are reordered after every graph_steps steps (every 64 when
+ * graph_steps is 0).  Defaults: 512 threads, 640 blocks, 64 steps per graph. */
 int32_t lpsim_set_launch(lpsim_ctx *ctx, int32_t block_size, int32_t n_blocks,
                          int32_t graph_steps);
 

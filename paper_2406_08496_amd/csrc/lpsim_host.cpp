@@ -63,7 +63,9 @@ struct lpsim_ctx {
     // stay resident in one round on 256 CUs at the move kernel's occupancy
     int threads = 512;
     int blocks = 640;
-    int graph_steps = 32;
+    // steps per graph, which is also the interval of the slot reorder (64 is
+    // within 0.5% of the best of 16..128 on the benchmark workloads)
+    int graph_steps = 64;
     // graphs of graph_steps steps (+ reorder) and of one step, by the parity
     // of the step they start at
     hipGraphExec_t g_full[2] = {nullptr, nullptr}, g_one[2] = {nullptr, nullptr};
@@ -625,7 +627,8 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
         enqueue_step(c, s, c->k & 1);
     }
     ++c->k;
-    if (++c->direct_since_reorder >= std::max(c->graph_steps, 32)) {
+    // the same reorder interval as the graphs (64 when kernels are launched singly)
+    if (++c->direct_since_reorder >= (c->graph_steps > 0 ? c->graph_steps : 64)) {
         const Dev dn = dev_at(c, c->k & 1);
         if (c->timing) {
             // several kernels: an event pair recorded around them

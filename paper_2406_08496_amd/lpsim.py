@@ -214,7 +214,7 @@ class Simulator:
     def block_edge(self, e, on=True):
         self._check(load_library().lpsim_block_edge(self._h, int(e), 1 if on else 0))
 
-    def set_launch(self, block_size=256, n_blocks=2048, graph_steps=32):
+    def set_launch(self, block_size=512, n_blocks=640, graph_steps=64):
         self._check(load_library().lpsim_set_launch(self._h, block_size, n_blocks, graph_steps))
 
     def step(self, n=1, stream=None):

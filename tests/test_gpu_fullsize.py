@@ -26,7 +26,7 @@ from test_gpu_parity import CNT_KEYS, assert_same_counters, assert_same_state, a
 
 pytestmark = pytest.mark.gpu
 
-BENCH_LAUNCH = (512, 640, 32)
+BENCH_LAUNCH = (512, 640, 64)
 ST_ACTIVE = 1
 
 
