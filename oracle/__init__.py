@@ -67,6 +67,7 @@ def _load():
         lib.or_load_network.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.or_load_trips.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
         lib.or_block_edge.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        lib.or_set_signals.argtypes = [vp] + [vp] * 5
         lib.or_step.argtypes = [vp, ctypes.c_int32]
         lib.or_place.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_float, ctypes.c_float]
@@ -153,6 +154,15 @@ class OracleSim:
 
     def block_edge(self, e, on=True):
         self._check(_load().or_block_edge(self._h, e, 1 if on else 0), "block_edge")
+
+    def set_signals(self, plan):
+        """Fixed-time signal plan (`synth.SignalPlan`), or None to remove it."""
+        if plan is None:
+            self._check(_load().or_set_signals(self._h, None, None, None, None, None), "set_signals")
+            return
+        arrs = [np.ascontiguousarray(getattr(plan, k), np.int32)
+                for k in ("n_phases", "green", "allred", "offset", "edge_phase")]
+        self._check(_load().or_set_signals(self._h, *[_ptr(a) for a in arrs]), "set_signals")
 
     def place(self, trip, rp, lane, x, v):
         """Test hook: put waiting `trip` on its route edge `rp` at (lane, x, v)."""

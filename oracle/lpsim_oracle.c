@@ -30,6 +30,17 @@
  *     behind the stop line.  Exclusive entry (Remarks, atomic switch) is
  *     resolved deterministically: the lowest trip id among all claimants of a
  *     target lane wins, departures and transfers pooled.
+ *   - Signal control (Algorithm 1 intersection branch; Section 3.3 keeps
+ *     signal states with the rest of a partition's local data).  The paper
+ *     gives no signal model, so this reading is a fixed-time plan per node:
+ *     n_phases phases, each `green` steps followed by `allred` steps, the
+ *     cycle shifted by `offset` steps; every approach edge of the node serves
+ *     in one phase (or in none: never stopped).  At step k the approach may
+ *     hand vehicles to the next edge only inside the green part of its phase;
+ *     otherwise the stop line is a standing obstacle, as for a full entry
+ *     window.  Departures (which enter at the upstream end of their first
+ *     edge) and arrivals (which leave at the end of the last edge) do not
+ *     pass a signal.
  *   - Departure (Algorithm 1, first test): a trip whose departure time has
  *     come enters its first edge when that edge's entry cells are free.
  *   - Mandatory lane change and gap acceptance (Section 3.1, Lane Change and
@@ -86,6 +97,9 @@ typedef struct {
     float *v0;
     int64_t *lane_off, *slot_off;
     uint8_t *blocked;
+    /* fixed-time signals (NULL: none): per node phases, green, all-red and
+       offset in steps; per edge the phase it is served in (-1 none) */
+    int32_t *sig_nph, *sig_green, *sig_allred, *sig_off, *sig_phase;
     int64_t map_bytes, n_slots;
     uint8_t *map;
     /* trips */
@@ -130,6 +144,7 @@ void or_destroy(or_sim *s) {
     free(s->src); free(s->dst); free(s->cells); free(s->lanes); free(s->rank);
     free(s->outdeg); free(s->v0); free(s->lane_off); free(s->slot_off);
     free(s->blocked); free(s->map);
+    free(s->sig_nph); free(s->sig_green); free(s->sig_allred); free(s->sig_off); free(s->sig_phase);
     free(s->depart); free(s->route_off); free(s->route); free(s->status);
     free(s->edge); free(s->lane); free(s->rp); free(s->enter_step);
     free(s->arrival_step); free(s->x); free(s->v); free(s->dep_order);
@@ -246,6 +261,54 @@ int or_load_network(or_sim *s, int32_t n_nodes, int32_t n_edges,
 int or_block_edge(or_sim *s, int32_t e, int32_t on) {
     if (!s || !s->loaded_net || e < 0 || e >= s->n_edges) return OR_EINVAL;
     s->blocked[e] = on ? 1 : 0;
+    return OR_OK;
+}
+
+static void drop_signals(or_sim *s) {
+    free(s->sig_nph); free(s->sig_green); free(s->sig_allred); free(s->sig_off); free(s->sig_phase);
+    s->sig_nph = s->sig_green = s->sig_allred = s->sig_off = s->sig_phase = NULL;
+}
+
+/* Install a fixed-time signal plan (copied), or remove it (n_phases NULL).
+ * Per node: n_phases (0 = no signal, else 1..15), green >= 1 and allred >= 0
+ * steps per phase, offset in [0, cycle) with cycle = n_phases*(green+allred)
+ * <= 65535.  Per edge: the phase of its downstream node it is served in,
+ * -1 for none (always -1 at a node without a signal). */
+int or_set_signals(or_sim *s, const int32_t *n_phases, const int32_t *green, const int32_t *allred,
+                   const int32_t *offset, const int32_t *edge_phase) {
+    if (!s || !s->loaded_net) return OR_EINVAL;
+    if (!n_phases) {
+        drop_signals(s);
+        return OR_OK;
+    }
+    if (!green || !allred || !offset || !edge_phase) return OR_EINVAL;
+    for (int32_t n = 0; n < s->n_nodes; n++) {
+        if (n_phases[n] < 0 || n_phases[n] > 15) return OR_EINVAL;
+        if (n_phases[n] == 0) continue;
+        if (green[n] < 1 || allred[n] < 0) return OR_EINVAL;
+        int64_t cyc = (int64_t)n_phases[n] * ((int64_t)green[n] + allred[n]);
+        if (cyc > 65535 || offset[n] < 0 || offset[n] >= cyc) return OR_EINVAL;
+    }
+    for (int32_t e = 0; e < s->n_edges; e++) {
+        int32_t np = n_phases[s->dst[e]];
+        if (edge_phase[e] < -1 || edge_phase[e] >= (np > 0 ? np : 0)) return OR_EINVAL;
+    }
+    drop_signals(s);
+    size_t nn = (size_t)s->n_nodes * 4, ne = (size_t)s->n_edges * 4;
+    s->sig_nph = (int32_t *)xcalloc(nn, 1);
+    s->sig_green = (int32_t *)xcalloc(nn, 1);
+    s->sig_allred = (int32_t *)xcalloc(nn, 1);
+    s->sig_off = (int32_t *)xcalloc(nn, 1);
+    s->sig_phase = (int32_t *)xcalloc(ne, 1);
+    if (!s->sig_nph || !s->sig_green || !s->sig_allred || !s->sig_off || !s->sig_phase) {
+        drop_signals(s);
+        return OR_ENOMEM;
+    }
+    memcpy(s->sig_nph, n_phases, nn);
+    memcpy(s->sig_green, green, nn);
+    memcpy(s->sig_allred, allred, nn);
+    memcpy(s->sig_off, offset, nn);
+    memcpy(s->sig_phase, edge_phase, ne);
     return OR_OK;
 }
 
@@ -377,6 +440,19 @@ static int entry_free(const or_sim *s, int32_t e, int32_t l) {
     for (int32_t c = 0; c < s->W; c++)
         if (s->map[cell_index(s, e, l, c)] != FREE_BYTE) return 0;
     return 1;
+}
+
+/* may vehicles on edge e pass its downstream signal at step k?  The node's
+ * cycle runs phase 0, 1, ... each for green + allred steps, starting at step
+ * -offset; edge e is served in its phase's first `green` steps. */
+static int approach_green(const or_sim *s, int32_t e, int32_t k) {
+    if (!s->sig_nph || s->sig_phase[e] < 0) return 1;
+    int32_t n = s->dst[e];
+    int64_t per = (int64_t)s->sig_green[n] + s->sig_allred[n];
+    int64_t cycle = per * s->sig_nph[n];
+    int64_t t = ((int64_t)k + s->sig_off[n]) % cycle;
+    int64_t phase = t / per, into = t % per;
+    return phase == s->sig_phase[e] && into < s->sig_green[n];
 }
 
 /* first occupied cell in cells lo..hi (inclusive) of lane l, or -1 */
@@ -532,7 +608,8 @@ static int step_once(or_sim *s) {
             if (!last && c + s->D >= C) {
                 int32_t en = s->route[s->route_off[i] + s->rp[i] + 1];
                 int32_t ln = l < s->lanes[en] - 1 ? l : s->lanes[en] - 1;
-                stop_line = !entry_free(s, en, ln);
+                /* a red signal, or a taken entry window, stops the vehicle */
+                stop_line = !approach_green(s, e, k) || !entry_free(s, en, ln);
             }
             if (stop_line) {
                 /* downstream entry occupied: a standing obstacle at the stop line */

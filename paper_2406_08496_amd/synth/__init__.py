@@ -399,3 +399,54 @@ def line_instance(lengths, speeds, lanes, departs, routes, n_nodes=None,
                     np.array(length, np.float32), np.array(ln, np.uint8),
                     np.array(speed, np.float32), np.array(departs, np.int32), off, re,
                     name="hand")
+
+
+# ----------------------------------------------------------------------------
+# fixed-time signal plans
+
+@dataclass
+class SignalPlan:
+    """Fixed-time signals: per node the number of phases (0 = no signal),
+    green and all-red steps per phase and the cycle offset in steps; per edge
+    the phase of its downstream node that serves it (-1 = none)."""
+
+    n_phases: np.ndarray  # int32 [n_nodes]
+    green: np.ndarray  # int32 [n_nodes]
+    allred: np.ndarray  # int32 [n_nodes]
+    offset: np.ndarray  # int32 [n_nodes]
+    edge_phase: np.ndarray  # int32 [E]
+
+    @property
+    def n_signals(self) -> int:
+        return int((self.n_phases > 0).sum())
+
+
+def signal_plan(inst: Instance, seed: int = 7, green_s: float = 40.0, allred_s: float = 5.0,
+                min_in: int = 3, dt: float = 0.5) -> SignalPlan:
+    """Two-phase fixed-time signals at every node with at least `min_in`
+    incoming edges: approaches arriving mostly along x are served in phase 0,
+    mostly along y in phase 1 (a node whose approaches all share one axis gets
+    no signal).  Cycle offsets are uniform over the cycle, seeded."""
+    rng = np.random.default_rng(seed)
+    n, E = inst.n_nodes, inst.n_edges
+    xy = inst.node_xy.astype(np.float64)
+    dxy = xy[inst.dst] - xy[inst.src]
+    axis = np.where(np.abs(dxy[:, 0]) >= np.abs(dxy[:, 1]), 0, 1).astype(np.int32)
+    indeg = np.bincount(inst.dst, minlength=n)
+    has = np.zeros((n, 2), bool)
+    has[inst.dst, axis] = True
+    sig = (indeg >= min_in) & has[:, 0] & has[:, 1]
+    green = max(1, int(round(green_s / dt)))
+    allred = max(0, int(round(allred_s / dt)))
+    cycle = 2 * (green + allred)
+    n_phases = np.where(sig, 2, 0).astype(np.int32)
+    offset = np.where(sig, rng.integers(0, cycle, size=n), 0).astype(np.int32)
+    edge_phase = np.where(sig[inst.dst], axis, -1).astype(np.int32)
+    return SignalPlan(n_phases, np.where(sig, green, 0).astype(np.int32),
+                      np.where(sig, allred, 0).astype(np.int32), offset, edge_phase)
+
+
+def concat_signal_plans(plans, insts) -> SignalPlan:
+    """One plan over a batch's concatenated nodes and edges."""
+    return SignalPlan(*[np.concatenate([getattr(p, k) for p in plans]).astype(np.int32)
+                        for k in ("n_phases", "green", "allred", "offset", "edge_phase")])

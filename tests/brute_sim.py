@@ -22,6 +22,9 @@ deterministic reading used throughout this project):
     (lane index capped by the next edge's lane count); departures request the
     lane (trip id mod lanes) of the first edge when its entry cells are free;
     per target lane the lowest trip id wins;
+  * a fixed-time signal at the end of an edge that is not serving it makes
+    the stop line a standing obstacle too (departures and arrivals pass no
+    signal);
   * lane change on the post-move positions, toward the lane given by the
     rank of the next edge among the node's out-edges, even steps toward lane
     0 only, odd steps away from it, with a hashed Bernoulli draw and lead/lag
@@ -85,7 +88,26 @@ class BruteSim:
         self.enter = [-1] * n
         self.arr = [-1] * n
         self.blocked = set()
+        self.signals = None  # synth.SignalPlan or None
         self.k = 0
+
+    def _green(self, e, k):
+        """Walk the node's cycle phase by phase (green, then all-red) from the
+        cycle position of step k; True if edge e is served at that moment."""
+        sp = self.signals
+        if sp is None or int(sp.edge_phase[e]) < 0:
+            return True
+        n = int(self.inst.dst[e])
+        g, r, nph = int(sp.green[n]), int(sp.allred[n]), int(sp.n_phases[n])
+        pos = (k + int(sp.offset[n])) % (nph * (g + r))
+        for ph in range(nph):
+            if pos < g:
+                return ph == int(sp.edge_phase[e])
+            pos -= g
+            if pos < r:
+                return False
+            pos -= r
+        raise AssertionError("position outside the cycle")
 
     # -- occupancy queries without a map ---------------------------------------
     def _occ(self, e, l, cells=None):
@@ -177,7 +199,7 @@ class BruteSim:
                 blocked = False
                 if not last and c + self.D >= C:
                     en = route[self.rp[i] + 1]
-                    blocked = self._entry_taken(en, min(l, self.nl[en] - 1))
+                    blocked = (not self._green(e, k)) or self._entry_taken(en, min(l, self.nl[en] - 1))
                 if blocked:
                     xn, vn = self._idm(x, v, self.v0[e], f32(C) - x, f32(0))
                     if xn > f32(C - 1):
