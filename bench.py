@@ -44,15 +44,19 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean over the 28,800
 # launches), each scaled by what the same counter reads for a plain 1 GiB
 # device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
-# Valid only for the kernel source it was taken on (sha256 below); otherwise
-# the bench reports null.  Commands and figures: profiles/k_move_regional_hbm_traffic.md
+# Valid only for the workload and the kernel source it was taken on (sha256
+# below); otherwise the bench reports null.  Commands and figures:
+# profiles/k_move_regional_hbm_traffic.md
+MOVE_TRAFFIC_WORKLOAD = "regional-225k-2.82M"
 MOVE_TRAFFIC = {"kernels_sha256": "f1459da57026d07a9792522bf5f74098942226e6bde253fa7d4fd6e5dce9cdb4",
                 "fetch_kib": 29227.16, "write_kib": 16419.04, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-def move_traffic_bytes():
+def move_traffic_bytes(workload=MOVE_TRAFFIC_WORKLOAD):
     import hashlib
 
+    if workload != MOVE_TRAFFIC_WORKLOAD:
+        return None
     src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
@@ -87,11 +91,13 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(inst, n_bins, budget_s):
+def cpu_baseline(inst, n_bins, budget_s, plan=None):
     """The oracle as it is, single thread, from step 0 until the budget runs out."""
     import oracle
 
     o = oracle.OracleSim(n_bins=n_bins).load(inst)
+    if plan is not None:
+        o.set_signals(plan)
     t0 = time.perf_counter()
     steps = 0
     while time.perf_counter() - t0 < budget_s and steps < inst.n_steps:
@@ -125,6 +131,8 @@ def main():
                     help="instance of the assignment comparison (default: the bench workload), "
                          "e.g. regional-demand:0.25 for the regional network at a quarter of the demand")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape first")
+    ap.add_argument("--signals", action="store_true",
+                    help="fixed-time two-phase signals at every node with 3+ approaches on both axes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM traffic counters")
     args = ap.parse_args()
@@ -162,6 +170,13 @@ def main():
     else:
         name, n_nodes, n_edges, n_trips = inst.name, inst.n_nodes, inst.n_edges, inst.n_trips
         n_route, horizon = int(inst.route_off[-1]), inst.n_steps
+    plan = None
+    if args.signals:
+        from paper_2406_08496_amd import synth
+
+        plan = (synth.concat_signal_plans([synth.signal_plan(i) for i in insts], insts) if batch
+                else synth.signal_plan(inst))
+        name += "+signals"
     K = args.steps if args.steps is not None else horizon
     W = args.warmup
     log(f"workload {name}: {n_nodes} nodes, {n_edges} edges, {n_trips} trips, "
@@ -174,6 +189,9 @@ def main():
         sim.load_batch(insts)
     else:
         sim.load(inst)
+    if plan is not None:
+        sim.set_signals(plan)
+        log(f"signals at {plan.n_signals} nodes")
     log(f"loaded in {time.perf_counter() - t:.1f} s")
     stream = torch.cuda.current_stream()
     tuned = None
@@ -230,7 +248,8 @@ def main():
         "config": {"workload": name, "nodes": n_nodes, "edges": n_edges,
                    "trips": n_trips, "dt": 0.5, "horizon_steps": horizon,
                    "block": tuned["block"] if tuned else args.block,
-                   "blocks": tuned["blocks"] if tuned else args.blocks, "graph_steps": args.graph_steps},
+                   "blocks": tuned["blocks"] if tuned else args.blocks, "graph_steps": args.graph_steps,
+                   "signalised_nodes": plan.n_signals if plan is not None else 0},
         "trips_per_s": c["arrived"] / (ms / 1e3),
         "arrived": c["arrived"],
         "vehicle_steps": vsteps,
@@ -253,7 +272,7 @@ def main():
         achieved = alg_bytes / (mv_ms / 1e3) / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": "k_move", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": move_traffic_bytes(),
+                           "traffic": move_traffic_bytes(name),
                            "bytes_per_launch": alg_bytes / max(mv_n, 1),
                            "avg_launch_us": mv_ms * 1e3 / max(mv_n, 1)}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
@@ -263,7 +282,7 @@ def main():
         log("kernel times:", json.dumps(out["kernel_ms"]))
 
     if not args.no_cpu_baseline and not batch:
-        out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget, plan)
         log("cpu baseline:", json.dumps(out["cpu_baseline"]))
     if args.assign and not batch:
         a_inst = inst if args.assign_workload is None else make_workload(args.assign_workload)[0]

@@ -205,6 +205,30 @@ int32_t lpsim_get_counters(lpsim_ctx *ctx, lpsim_counters *out);
  * (Section 3.1 Remarks, intersection modelling).  Input edge id. */
 int32_t lpsim_block_edge(lpsim_ctx *ctx, int32_t edge, int32_t on);
 
+/* Fixed-time signal plan (Algorithm 1 intersection branch: a vehicle at an
+ * intersection proceeds as the node's signal allows; Section 3.3 keeps
+ * signal states as local data).  The paper gives no signal model; this is a
+ * fixed-time reading.  Node n runs n_phases[n] phases in turn, each
+ * green[n] steps of green followed by allred[n] steps in which no phase is
+ * served; at step k the cycle position is (k + offset[n]) mod cycle, with
+ * cycle = n_phases[n] * (green[n] + allred[n]).  Edge e is served in phase
+ * edge_phase[e] of its downstream node (-1: never stopped).  Outside its
+ * green the stop line of e is a standing obstacle, as for a full entry
+ * window: vehicles stop before it and make no entry request.  Departures
+ * and arrivals pass no signal.
+ *   n_phases, green, allred, offset   host, int32 [n_nodes]: 0..15 phases
+ *       (0: no signal; the other three then ignored), green >= 1,
+ *       allred >= 0, cycle <= 65535, 0 <= offset < cycle
+ *   edge_phase   host, int32 [n_edges], input edge ids: -1 or a phase
+ *       0..n_phases-1 of the edge's downstream node
+ * Batched contexts take all scenarios' nodes and edges in input order (node
+ * ids offset by node_off).  n_phases NULL removes the plan.  Arrays are
+ * copied; the plan applies from the next step and survives reloads of trips
+ * and state restores.  Errors: ESTATE (no network), EINVAL (the first bad
+ * entry is named in lpsim_last_error), ENOMEM, EDEVICE. */
+int32_t lpsim_set_signals(lpsim_ctx *ctx, const int32_t *n_phases, const int32_t *green,
+                          const int32_t *allred, const int32_t *offset, const int32_t *edge_phase);
+
 /* Launch shape: threads per block (64..1024, multiple of 64), blocks per
  * vehicle kernel (multiple of 8, up to 8192), steps captured per HIP graph
  * (>= 1; 0 launches kernels one by one).  Results do not depend on these.

@@ -81,6 +81,7 @@ struct Slots {
 
 constexpr uint32_t NO_NEXT = 0xffffffffu;
 constexpr uint32_t CD_NEXT_BLOCKED = 1u << 31;  // the next edge accepts no entries
+constexpr uint32_t CD_SIGNAL = 1u << 30;        // the current edge ends at a signal serving it
 
 struct Dev {
     Params p;
@@ -109,6 +110,10 @@ struct Dev {
     uint32_t *blk_ev;   // [MAX_BLOCKS] any entry or exit in the block this step
     const uint4 *edge;
     uint32_t *aux;
+    // fixed-time signal of each approach edge (null: no signals):
+    // x = cycle | offset << 16, y = green start | green end << 16, in steps of
+    // the cycle; x = 0 for an edge no signal stops
+    const uint2 *sig;
     int32_t n_scen;       // scenarios in this context (1 unless batched)
     const int32_t *escen;
     const uint64_t *scen_seed;
@@ -163,6 +168,8 @@ constexpr int PART_ROWS = MAX_BLOCKS + (int)MAX_HELPERS;
 
 // refresh the cached blocked flag of vehicles heading for (internal) `edge`
 void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s);
+// recompute the cached signal and blocked flags of every live vehicle
+void launch_refresh_flags(const Dev &d, hipStream_t s);
 // move (with departure requests in helper blocks)
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 // resolve (with departures in helper blocks)

@@ -45,6 +45,7 @@ struct lpsim_ctx {
     std::vector<int32_t> int_of_ext;           // global input edge id -> internal
     std::vector<int32_t> src_g, dst_g;         // global input edge order, local node ids
     std::vector<uint32_t> aux_h;               // internal order
+    uint2 *sig_d = nullptr;                    // signal words (allocated on first use)
     int32_t n_edges = 0;
     uint64_t map_bytes = 0;
     uint32_t n_lane_slots = 0;
@@ -201,6 +202,8 @@ static void release_trips(lpsim_ctx *c) {
 static void release_net(lpsim_ctx *c) {
     release_trips(c);
     dev_free_all(c, c->net_allocs);
+    c->sig_d = nullptr;
+    c->d.sig = nullptr;
     c->have_net = false;
 }
 
@@ -985,6 +988,54 @@ int32_t lpsim_block_edge(lpsim_ctx *c, int32_t edge, int32_t on) {
     return LPSIM_OK;
 }
 
+int32_t lpsim_set_signals(lpsim_ctx *c, const int32_t *n_phases, const int32_t *green, const int32_t *allred,
+                          const int32_t *offset, const int32_t *edge_phase) {
+    int32_t rc = check_ready(c, false);
+    if (rc) return rc;
+    const int32_t E = c->n_edges;
+    std::vector<uint2> w((size_t)E, make_uint2(0u, 0u));
+    if (n_phases) {
+        if (!green || !allred || !offset || !edge_phase) return fail(c, LPSIM_EINVAL, "null signal array");
+        const int32_t n_nodes = c->node_off[c->n_scen];
+        for (int32_t n = 0; n < n_nodes; ++n) {
+            if (n_phases[n] < 0 || n_phases[n] > 15) return fail(c, LPSIM_EINVAL, "node %d: phases not in 0..15", n);
+            if (n_phases[n] == 0) continue;
+            if (green[n] < 1 || allred[n] < 0) return fail(c, LPSIM_EINVAL, "node %d: bad green or all-red", n);
+            const int64_t cyc = (int64_t)n_phases[n] * ((int64_t)green[n] + allred[n]);
+            if (cyc > 65535) return fail(c, LPSIM_EINVAL, "node %d: cycle above 65535 steps", n);
+            if (offset[n] < 0 || offset[n] >= cyc) return fail(c, LPSIM_EINVAL, "node %d: offset outside the cycle", n);
+        }
+        for (int32_t s = 0; s < c->n_scen; ++s) {
+            for (int32_t e = c->edge_off[s]; e < c->edge_off[s + 1]; ++e) {
+                const int32_t n = c->node_off[s] + c->dst_g[e];
+                const int32_t ph = edge_phase[e];
+                if (ph < -1 || ph >= n_phases[n]) return fail(c, LPSIM_EINVAL, "edge %d: phase not served by its node", e);
+                if (ph < 0) continue;
+                const uint32_t per = (uint32_t)(green[n] + allred[n]);
+                const uint32_t cyc = per * (uint32_t)n_phases[n];
+                const uint32_t g0 = (uint32_t)ph * per;
+                w[(size_t)c->int_of_ext[e]] = make_uint2(cyc | ((uint32_t)offset[n] << 16),
+                                                         g0 | ((g0 + (uint32_t)green[n]) << 16));
+            }
+        }
+    }
+    if ((rc = sync_all(c))) return rc;
+    if (n_phases) {
+        if (!c->sig_d && (rc = alloc_n(c, c->sig_d, (size_t)E, c->net_allocs))) return rc;
+        HIPCHK(c, hipMemcpy(c->sig_d, w.data(), (size_t)E * sizeof(uint2), hipMemcpyHostToDevice));
+    }
+    c->d.sig = n_phases ? c->sig_d : nullptr;
+    // captured graphs hold the old device view
+    drop_graphs(c);
+    if (c->have_trips) {
+        // vehicles already on the road carry the flag of their edge
+        launch_refresh_flags(dev_at(c, c->k & 1), c->own);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(c->own));
+    }
+    return LPSIM_OK;
+}
+
 int32_t lpsim_set_launch(lpsim_ctx *c, int32_t block_size, int32_t n_blocks, int32_t graph_steps) {
     if (!c) return LPSIM_EINVAL;
     if (block_size < 64 || block_size > 1024 || block_size % 64 || n_blocks < 8 || n_blocks > MAX_BLOCKS ||
@@ -1155,6 +1206,10 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
     HIPCHK(c, hipMemcpy(d.ctrl + (ct.k & 1), &ct, sizeof ct, hipMemcpyHostToDevice));
     c->k = ct.k;
+    // the snapshot's cached edge flags follow the signal plan and blocked
+    // edges of now, not of when it was taken
+    launch_refresh_flags(dev_at(c, c->k & 1), c->own);
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipDeviceSynchronize());
     return LPSIM_OK;
 }

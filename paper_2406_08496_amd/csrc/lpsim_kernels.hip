@@ -370,13 +370,27 @@ __device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int3
 // ---------------------------------------------------------------------------
 // move: longitudinal intent from step-k state
 
+// may vehicles pass the signal at the end of their edge at step k?  w is the
+// edge's signal word: the cycle position of step k must lie in the green
+// part of the phase that serves the edge
+__device__ __forceinline__ bool signal_green(uint2 w, int32_t k) {
+    const uint32_t cyc = w.x & 0xffffu, off = w.x >> 16;
+    const uint32_t t = ((uint32_t)k % cyc + off) % cyc;
+    return t >= (w.y & 0xffffu) && t < (w.y >> 16);
+}
+
+__device__ __forceinline__ bool has_signal(const Dev &d, int32_t e) {
+    return d.sig != nullptr && d.sig[e].x != 0u;
+}
+
 // refresh a vehicle's cached edge data: it is on edge `e` (record E) in
 // `lane`, next edge `en` (-1 on the last edge)
-__device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t i, const uint4 &E, uint32_t lane,
-                                          int32_t en) {
+__device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t i, int32_t e, const uint4 &E,
+                                          uint32_t lane, int32_t en) {
     S.lb[i] = lane_base(E, lane);
     S.v0[i] = __uint_as_float(E.z);
     uint32_t cd = (uint32_t)E_CELLS(E) | ((uint32_t)E_LOOK(E) << 16);
+    if (has_signal(d, e)) cd |= CD_SIGNAL;
     if (en >= 0) {
         const uint4 En = d.edge[en];
         if (d.aux[en] & AUX_BLOCKED) cd |= CD_NEXT_BLOCKED;
@@ -483,8 +497,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
                 } else {
                     bool stop = false;
                     if (near) {
-                        // the next edge's entry window (its blocked flag is cached)
-                        stop = (cd & CD_NEXT_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
+                        // a red signal at the stop line (edge id and signal
+                        // word read only here), or the next edge's entry
+                        // window taken (its blocked flag is cached)
+                        if (cd & CD_SIGNAL) {
+                            stop = !signal_green(d.sig[S.e[i]], k);
+                            scanned += 12u;
+                        }
+                        stop = stop || (cd & CD_NEXT_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
                         scanned += (uint32_t)p.W;
                     }
                     if (stop) {
@@ -611,7 +631,7 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             S.rp[ns] = r0;
             S.rend[ns] = rend;
             S.ent[ns] = k + 1;
-            set_cache(d, S, ns, E0, l0, en0);
+            set_cache(d, S, ns, e0, E0, l0, en0);
             d.map[o.y] = speed_byte(0.0f);
             add_entry(d, e0, k + 1);
             atomicAdd(&cnt.c[P_DEPARTS], 1u);
@@ -697,7 +717,7 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
             S.rp[i] = rp;
             S.ent[i] = k + 1;
             S.m[i] = ln | M_ENTERED | (req2 << M_REQ_SHIFT);
-            set_cache(d, S, i, En, ln, en2);
+            set_cache(d, S, i, en, En, ln, en2);
             atomicAdd(&cnt.c[P_TRANSFERS], 1u);
             s_ev = 1;
         } else {
@@ -1021,6 +1041,26 @@ __global__ __launch_bounds__(1024) void k_set_next_blocked(Dev d, int32_t edge, 
 
 void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s) {
     hipLaunchKernelGGL(k_set_next_blocked, dim3(1024), dim3(256), 0, s, d, edge, on ? 1u : 0u);
+}
+
+// both cached edge flags of every live vehicle, recomputed from the edge
+// state (after a signal plan change or a restored snapshot)
+__global__ __launch_bounds__(1024) void k_refresh_flags(Dev d) {
+    const Ctrl *ctl = d.ctrl;
+    const uint32_t n = ctl->n_slots;
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (S.m[i] & M_DEAD) continue;
+        const int32_t en = S.en[i];
+        uint32_t cd = S.cd[i] & ~(CD_SIGNAL | CD_NEXT_BLOCKED);
+        if (has_signal(d, S.e[i])) cd |= CD_SIGNAL;
+        if (en >= 0 && (d.aux[en] & AUX_BLOCKED)) cd |= CD_NEXT_BLOCKED;
+        S.cd[i] = cd;
+    }
+}
+
+void launch_refresh_flags(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh_flags, dim3(1024), dim3(256), 0, s, d);
 }
 
 // ---------------------------------------------------------------------------

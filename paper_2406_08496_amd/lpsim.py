@@ -67,6 +67,7 @@ SIGNATURES = {
     "lpsim_get_vehicles": ([_vp] + [_vp] * 7, _i32),
     "lpsim_get_counters": ([_vp, ctypes.POINTER(Counters)], _i32),
     "lpsim_block_edge": ([_vp, _i32, _i32], _i32),
+    "lpsim_set_signals": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_set_launch": ([_vp, _i32, _i32, _i32], _i32),
     "lpsim_set_timing": ([_vp, _i32], _i32),
     "lpsim_kernel_times": ([_vp, _vp, _vp, _i32], _i32),
@@ -213,6 +214,16 @@ class Simulator:
     # -- running
     def block_edge(self, e, on=True):
         self._check(load_library().lpsim_block_edge(self._h, int(e), 1 if on else 0))
+
+    def set_signals(self, plan):
+        """Fixed-time signal plan with fields n_phases, green, allred, offset
+        (per node) and edge_phase (per edge), or None to remove it."""
+        if plan is None:
+            self._check(load_library().lpsim_set_signals(self._h, None, None, None, None, None))
+            return
+        arrs = [np.ascontiguousarray(getattr(plan, k), np.int32)
+                for k in ("n_phases", "green", "allred", "offset", "edge_phase")]
+        self._check(load_library().lpsim_set_signals(self._h, *[_p(a) for a in arrs]))
 
     def set_launch(self, block_size=512, n_blocks=640, graph_steps=64):
         self._check(load_library().lpsim_set_launch(self._h, block_size, n_blocks, graph_steps))

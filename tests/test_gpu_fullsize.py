@@ -1,7 +1,8 @@
 """The benchmark workloads at their full sizes, in the launch configuration
 the benchmark times: regional (225,150 nodes, 550,000 edges, 2.82M trips,
-28,800 steps), large (1M nodes, 2.5M edges, 9M trips, 36,000 steps) and the
-batch of 64 scenarios (4.4M edges, 7.6M trips, 14,400 steps).
+28,800 steps), the same with fixed-time signals, large (1M nodes, 2.5M
+edges, 9M trips, 36,000 steps) and the batch of 64 scenarios (4.4M edges,
+7.6M trips, 14,400 steps).
 
 The oracle cannot run the whole horizon in test time, so the check has two
 parts:
@@ -99,14 +100,19 @@ def properties_to_horizon(gpu, inst, horizon, every=2400, start=2400, edge_base=
     return c
 
 
-@pytest.mark.parametrize("workload", ["regional", "large"])
+@pytest.mark.parametrize("workload", ["regional", "large", "regional+signals"])
 def test_full_size(Sim, workload):
-    inst, n_bins = (synth.regional(), 48) if workload == "regional" else (synth.large(), 60)
+    inst, n_bins = (synth.large(), 60) if workload == "large" else (synth.regional(), 48)
+    plan = synth.signal_plan(inst) if workload.endswith("+signals") else None
     case(workload, "full size:", inst.n_nodes, "nodes,", inst.n_edges, "edges,", inst.n_trips, "trips")
     gpu = Sim(n_bins=n_bins)
     gpu.set_launch(*BENCH_LAUNCH)
     gpu.load(inst)
     ref = oracle.OracleSim(n_bins=n_bins).load(inst)
+    if plan is not None:
+        case("signals at", plan.n_signals, "nodes")
+        gpu.set_signals(plan)
+        ref.set_signals(plan)
     for k in (1200, 2400):
         gpu.step(1200)
         ref.step(1200)

@@ -37,6 +37,9 @@ def test_bench_byte_model_and_traffic_key():
         assert t == pytest.approx((m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024)
     else:
         assert t is None  # counters were taken on another kernel source
+    # and on one workload only
+    assert bench.move_traffic_bytes("large-x1.0") is None
+    assert bench.move_traffic_bytes(bench.MOVE_TRAFFIC_WORKLOAD + "+signals") is None
 
 
 def test_bench_workload_names():
