@@ -46,7 +46,12 @@
  *   - Mandatory lane change and gap acceptance (Section 3.1, Lane Change and
  *     Gap Acceptance equations): the probability ramps up linearly inside x0
  *     of the edge end; critical lead/lag gaps are linear in the anticipation
- *     times alpha with zero random terms.
+ *     times alpha.  The equations' random components eps_a, eps_b (notation
+ *     table) have no stated distribution; here each is uniform on
+ *     [-eps, eps), drawn per attempt from a second counter-based stream, and
+ *     enters the speed term of the critical gap before its clamp at zero, so
+ *     a critical gap never falls below g_a (g_b).  eps = 0 (the default)
+ *     leaves the terms out.
  *   - Edge entry time t_start (Algorithm 1, new-edge bookkeeping) gives the
  *     per-edge travel times; travel-time estimation is the simulator's stated
  *     purpose (abstract).
@@ -79,6 +84,7 @@ typedef struct {
     uint64_t seed;
     int32_t free_mode;   /* 0: speed jumps to v0 without a leader; 1: IDM free road */
     int32_t lane_change; /* 0 off, 1 on */
+    float eps_a, eps_b;  /* half-widths of the random lead / lag gap terms (0: none) */
 } or_params;
 
 typedef struct {
@@ -162,6 +168,7 @@ int or_create(const or_params *p, or_sim **out) {
     if (!(p->dt > 0 && p->a > 0 && p->b > 0 && p->s0 > 0 && p->T > 0 &&
           p->veh_len > 0 && p->x0 > 0 && p->g_a >= 0 && p->g_b >= 0 &&
           p->alpha_i >= 0 && p->alpha_a >= 0 && p->alpha_b >= 0 &&
+          p->eps_a >= 0 && p->eps_a <= 100 && p->eps_b >= 0 && p->eps_b <= 100 &&
           p->bin_seconds > 0 && p->delta == 4 && p->n_bins >= 1 &&
           (p->free_mode == 0 || p->free_mode == 1) &&
           (p->lane_change == 0 || p->lane_change == 1)))
@@ -470,6 +477,9 @@ static int32_t scan_backward(const or_sim *s, int32_t e, int32_t l, int32_t hi, 
 }
 
 /* SplitMix64 output function (Steele, Lea & Flood 2014) */
+/* key of the stream of the random gap terms (an arbitrary odd constant) */
+#define EPS_STREAM 0xD6E8FEB86659FD93ull
+
 static uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
@@ -759,6 +769,16 @@ static int step_once(or_sim *s) {
             uint64_t h = mix64(p->seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)k));
             if (!((float)(h >> 40) < prob * 16777216.0f)) continue;
             s->c.lc_attempts++;
+            /* random gap terms: a second stream keyed by the same (trip, step);
+               the top 24 bits give eps_a, the next 24 eps_b, each uniform on
+               [-eps, eps) in steps of eps * 2^-23 */
+            float ea = 0.0f, eb = 0.0f;
+            if (p->eps_a > 0.0f || p->eps_b > 0.0f) {
+                uint64_t h2 = mix64(p->seed ^ EPS_STREAM ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)k));
+                float ua = (float)(h2 >> 40), ub = (float)((h2 >> 16) & 0xffffffu);
+                ea = p->eps_a * (ua * 0x1p-23f - 1.0f);
+                eb = p->eps_b * (ub * 0x1p-23f - 1.0f);
+            }
             int32_t lt = l + dir;
             int32_t c = (int32_t)floorf(x);
             int32_t C = s->cells[e];
@@ -769,7 +789,7 @@ static int step_once(or_sim *s) {
             if (ca >= 0) {
                 float va = (float)s->map[cell_index(s, e, lt, ca)];
                 float g_lead = ((float)ca - x) - L;
-                float crit = p->g_a + max0f((p->alpha_i * v) - (p->alpha_a * va));
+                float crit = p->g_a + max0f(((p->alpha_i * v) - (p->alpha_a * va)) + ea);
                 if (!(g_lead >= crit)) ok = 0;
             }
             int32_t lo = c - s->D > 0 ? c - s->D : 0;
@@ -777,7 +797,7 @@ static int step_once(or_sim *s) {
             if (ok && cb >= 0) {
                 float vb = (float)s->map[cell_index(s, e, lt, cb)];
                 float g_lag = (x - L) - (float)(cb + 1);
-                float crit = p->g_b + max0f((p->alpha_b * vb) - (p->alpha_i * v));
+                float crit = p->g_b + max0f(((p->alpha_b * vb) - (p->alpha_i * v)) + eb);
                 if (!(g_lag >= crit)) ok = 0;
             }
             if (ok) {

@@ -28,7 +28,8 @@ deterministic reading used throughout this project):
   * lane change on the post-move positions, toward the lane given by the
     rank of the next edge among the node's out-edges, even steps toward lane
     0 only, odd steps away from it, with a hashed Bernoulli draw and lead/lag
-    gap acceptance.
+    gap acceptance; the critical gaps' random terms are uniform on
+    [-eps, eps) from a second hashed stream, added before the clamp at zero.
 """
 from __future__ import annotations
 
@@ -38,6 +39,7 @@ import numpy as np
 
 f32 = np.float32
 MASK64 = (1 << 64) - 1
+EPS_STREAM = 0xD6E8FEB86659FD93  # key of the random gap terms' stream
 
 
 def splitmix_out(z: int) -> int:
@@ -50,13 +52,14 @@ def splitmix_out(z: int) -> int:
 class BruteSim:
     def __init__(self, inst, dt=0.5, a=1.0, b=1.5, s0=2.0, T=1.5, veh_len=5.0,
                  x0=100.0, g_a=2.0, g_b=2.0, alpha_i=1.0, alpha_a=1.0, alpha_b=1.0,
-                 seed=0x5EED, free_mode=0, lane_change=1, **_ignored):
+                 seed=0x5EED, free_mode=0, lane_change=1, eps_a=0.0, eps_b=0.0, **_ignored):
         self.inst = inst
         self.dt, self.a, self.b, self.s0, self.T = f32(dt), f32(a), f32(b), f32(s0), f32(T)
         self.L, self.x0 = f32(veh_len), f32(x0)
         self.g_a, self.g_b = f32(g_a), f32(g_b)
         self.al_i, self.al_a, self.al_b = f32(alpha_i), f32(alpha_a), f32(alpha_b)
         self.seed = seed
+        self.eps_a, self.eps_b = f32(eps_a), f32(eps_b)
         self.free_mode = free_mode
         self.lane_change = lane_change
         self.W = math.ceil(float(f32(veh_len)) + float(f32(s0)))
@@ -278,6 +281,13 @@ class BruteSim:
                 h = splitmix_out(self.seed ^ ((i << 32) | (k & 0xFFFFFFFF)))
                 if not (f32(h >> 40) < p * f32(16777216.0)):
                     continue
+                ea = eb = f32(0)
+                if self.eps_a > 0 or self.eps_b > 0:
+                    # second stream, same (trip, step) key: 24 bits per term
+                    h2 = splitmix_out(self.seed ^ EPS_STREAM ^ ((i << 32) | (k & 0xFFFFFFFF)))
+                    ua, ub = h2 >> 40, (h2 >> 16) & 0xFFFFFF
+                    ea = self.eps_a * (f32(ua) / f32(2 ** 23) - f32(1))
+                    eb = self.eps_b * (f32(ub) / f32(2 ** 23) - f32(1))
                 lt = l + d
                 c = int(math.floor(float(x)))
                 o = occ(e, lt)
@@ -287,13 +297,13 @@ class BruteSim:
                 ca = self._first_ahead(o, c + 1, min(c + self.D, self.C[e] - 1))
                 if ca is not None:
                     va = f32(o[ca])
-                    need = self.g_a + max(f32(0), (self.al_i * v) - (self.al_a * va))
+                    need = self.g_a + max(f32(0), ((self.al_i * v) - (self.al_a * va)) + ea)
                     if not ((f32(ca) - x) - self.L >= need):
                         ok = False
                 cb = self._first_behind(o, c - 1, max(0, c - self.D))
                 if ok and cb is not None:
                     vb = f32(o[cb])
-                    need = self.g_b + max(f32(0), (self.al_b * vb) - (self.al_i * v))
+                    need = self.g_b + max(f32(0), ((self.al_b * vb) - (self.al_i * v)) + eb)
                     if not ((x - self.L) - f32(cb + 1) >= need):
                         ok = False
                 if ok:

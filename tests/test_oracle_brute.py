@@ -92,3 +92,12 @@ def test_brute_signals(seed, green_s, allred_s):
     free = oracle.OracleSim().load(inst)
     free.step(300)
     assert o.counters()["vehicle_steps"] > free.counters()["vehicle_steps"]
+
+
+@pytest.mark.parametrize("seed,eps_a,eps_b", [(8, 1.0, 0.0), (9, 0.5, 3.0), (10, 4.0, 4.0)])
+def test_brute_random_gap_terms(seed, eps_a, eps_b):
+    """Random lead/lag gap terms: the brute-force simulator draws them with its
+    own hash code; equal state at every step."""
+    inst = synth.grid_instance(seed=seed, side=3, n_trips=250, depart_window=80, len_lo=15, len_hi=60, lanes=3)
+    o = compare_run(inst, 400, seed=seed * 31, eps_a=eps_a, eps_b=eps_b)
+    assert o.counters()["lc_accepts"] > 0

@@ -299,3 +299,63 @@ def test_stats_identities_grid(tiny_grid):
     free = np.ceil(np.ceil(tiny_grid.length) / (tiny_grid.speed.astype(np.float64) * 0.5))
     used = st["n_exits"] > 0
     assert np.all(st["tt_sum"][used] >= free[used] * st["n_exits"][used] - st["n_exits"][used])
+
+
+# --- random gap terms ---------------------------------------------------------------
+
+def lc_rate(xb, trials, lead=True, lag_cell=None, **params):
+    """Fraction of seeds for which vehicle B changes lane in the first step."""
+    n = 4
+    inst = synth.line_instance([200, 50], [16.0, 16.0], [2, 2], [10**6] * n, [[0, 1]] * n)
+    ok = 0
+    for seed in range(1, trials + 1):
+        o = oracle.OracleSim(x0=1.0e6, seed=seed * 7919, **params).load(inst)
+        o.block_edge(1)
+        o.place(0, 0, 1, xb, 0.0)
+        o.place(1, 0, 1, 196.0, 0.0)
+        if lead:
+            o.place(2, 0, 0, 198.0, 0.0)
+        if lag_cell is not None:
+            o.place(3, 0, 0, float(lag_cell), 0.0)
+        o.step(1)
+        assert o.counters()["lc_attempts"] >= 1
+        ok += int(o.vehicles()["lane"][0] == 0)
+    return ok / trials
+
+
+@pytest.mark.parametrize("xb,eps,p_accept", [
+    (191.0, 1.0, 0.5),    # lead gap = g_a: accepted iff eps_a <= 0
+    (190.5, 1.0, 0.75),   # gap g_a + 0.5 with eps_a uniform on [-1, 1)
+    (190.0, 1.0, 1.0),    # gap g_a + 1: every draw accepts
+    # gap g_a - 1: no draw helps, since the clamp keeps the critical gap >= g_a
+    # (a term added after the clamp would accept a third of the draws)
+    (192.0, 3.0, 0.0),
+])
+def test_lead_random_term_is_uniform(xb, eps, p_accept):
+    """Everyone at rest, so the speed term is 0 and the critical lead gap is
+    g_a + max(0, eps_a): the acceptance rate over seeds is the uniform law's
+    P(eps_a <= gap - g_a)."""
+    rate = lc_rate(xb, 400, eps_a=eps)
+    assert abs(rate - p_accept) < 0.08
+
+
+def test_lag_random_term_is_uniform():
+    # lag gap exactly g_b (lag vehicle at cell 183): accepted iff eps_b <= 0
+    assert abs(lc_rate(191.0, 400, lead=False, lag_cell=183, eps_b=2.0) - 0.5) < 0.08
+    # eps_b only: the lead side keeps its deterministic threshold (gap g_a accepted)
+    assert lc_rate(191.0, 50, eps_b=2.0) == 1.0
+
+
+def test_random_terms_zero_change_nothing():
+    inst = synth.grid_instance(seed=3, side=4, n_trips=500, depart_window=120, len_lo=20, len_hi=80, lanes=3)
+    a = oracle.OracleSim().load(inst)
+    b = oracle.OracleSim(eps_a=0.0, eps_b=0.0).load(inst)
+    c = oracle.OracleSim(eps_a=1.5, eps_b=1.5).load(inst)
+    a.step(500)
+    b.step(500)
+    c.step(500)
+    va, vb, vc = a.vehicles(), b.vehicles(), c.vehicles()
+    for key in ("status", "edge", "lane", "x", "v"):
+        assert np.array_equal(va[key], vb[key])
+    # and nonzero terms do change the lane-change outcomes
+    assert a.counters()["lc_accepts"] != c.counters()["lc_accepts"]
