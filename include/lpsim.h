@@ -75,6 +75,12 @@ typedef struct lpsim_ctx lpsim_ctx;
  *   seed      seed of the hashed lane-change draws
  *   free_mode LPSIM_FREE_JUMP or LPSIM_FREE_IDM
  *   lane_change   1 to enable mandatory lane changes, 0 to disable
+ *   eps_a, eps_b  random components of the critical lead / lag gaps (Gap
+ *             Acceptance equations; their law is not given): each is uniform
+ *             on [-eps, eps), drawn per attempt from a second hashed stream
+ *             of (seed, trip, step), and enters the speed term before its
+ *             clamp at zero, so a critical gap stays >= g_a (g_b).  0..100;
+ *             0 (the default) leaves the term out.
  */
 typedef struct {
     float dt, a, b, s0, T, veh_len, x0, g_a, g_b, alpha_i, alpha_a, alpha_b;
@@ -84,6 +90,7 @@ typedef struct {
     uint64_t seed;
     int32_t free_mode;
     int32_t lane_change;
+    float eps_a, eps_b;
 } lpsim_params;
 
 typedef struct {

@@ -39,6 +39,7 @@ constexpr int MAX_BLOCKS = 8192;
 
 struct Params {
     float dt, a, b, s0, T, L, x0, g_a, g_b, al_i, al_a, al_b;
+    float eps_a, eps_b;  // half-widths of the random gap terms (0: none)
     float tsab;     // 2 sqrt(a b), rounded once from fp64
     float half_dt;  // 0.5 dt
     int32_t W;      // entry window in cells

@@ -696,6 +696,7 @@ int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out) {
     *out = nullptr;
     if (!(p->dt > 0 && p->a > 0 && p->b > 0 && p->s0 > 0 && p->T > 0 && p->veh_len > 0 && p->x0 > 0 &&
           p->g_a >= 0 && p->g_b >= 0 && p->alpha_i >= 0 && p->alpha_a >= 0 && p->alpha_b >= 0 &&
+          p->eps_a >= 0 && p->eps_a <= 100 && p->eps_b >= 0 && p->eps_b <= 100 &&
           p->bin_seconds > 0 && p->delta == 4 && p->n_bins >= 1 &&
           (p->free_mode == LPSIM_FREE_JUMP || p->free_mode == LPSIM_FREE_IDM) &&
           (p->lane_change == 0 || p->lane_change == 1)))
@@ -710,6 +711,7 @@ int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out) {
     dp.dt = p->dt; dp.a = p->a; dp.b = p->b; dp.s0 = p->s0; dp.T = p->T; dp.L = p->veh_len;
     dp.x0 = p->x0; dp.g_a = p->g_a; dp.g_b = p->g_b;
     dp.al_i = p->alpha_i; dp.al_a = p->alpha_a; dp.al_b = p->alpha_b;
+    dp.eps_a = p->eps_a; dp.eps_b = p->eps_b;
     dp.tsab = (float)(2.0 * std::sqrt((double)p->a * (double)p->b));
     dp.half_dt = 0.5f * p->dt;
     dp.W = (int32_t)std::ceil((double)p->veh_len + (double)p->s0);

@@ -219,6 +219,9 @@ __device__ __forceinline__ void free_move(const Params &p, float x, float v, flo
     }
 }
 
+// key of the random gap terms' hash stream (an arbitrary odd constant)
+constexpr uint64_t GAP_TERM_KEY = 0xD6E8FEB86659FD93ull;
+
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     // SplitMix64 output function (Steele, Lea & Flood 2014)
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
@@ -798,6 +801,14 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             const uint64_t h = mix64(seed ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
             if (!((float)(h >> 40) < prob * 16777216.0f)) break;
             atomicAdd(&cnt.c[P_LC_TRY], 1u);
+            // random gap terms from a second stream of the same key: 24 bits
+            // each, uniform on [-eps, eps) in steps of eps * 2^-23
+            float ea = 0.0f, eb = 0.0f;
+            if (p.eps_a > 0.0f || p.eps_b > 0.0f) {
+                const uint64_t h2 = mix64(seed ^ GAP_TERM_KEY ^ (((uint64_t)loc << 32) | (uint64_t)(uint32_t)k));
+                ea = p.eps_a * ((float)(uint32_t)(h2 >> 40) * 0x1p-23f - 1.0f);
+                eb = p.eps_b * ((float)(uint32_t)((h2 >> 16) & 0xffffffu) * 0x1p-23f - 1.0f);
+            }
             const int32_t lt = lane + dir;
             const int32_t c = (int32_t)x;
             const uint32_t lb = lb0 + (uint32_t)(dir * C);  // lane lt of the same edge
@@ -811,7 +822,7 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             if (ca >= 0) {
                 const float va = (float)vtmp;
                 const float g_lead = ((float)ca - x) - p.L;
-                const float t = (p.al_i * v) - (p.al_a * va);
+                const float t = ((p.al_i * v) - (p.al_a * va)) + ea;
                 const float crit = p.g_a + (t > 0.0f ? t : 0.0f);
                 if (!(g_lead >= crit)) break;
             }
@@ -820,7 +831,7 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             if (cb >= 0) {
                 const float vb = (float)vtmp;
                 const float g_lag = (x - p.L) - (float)(cb + 1);
-                const float t = (p.al_b * vb) - (p.al_i * v);
+                const float t = ((p.al_b * vb) - (p.al_i * v)) + eb;
                 const float crit = p.g_b + (t > 0.0f ? t : 0.0f);
                 if (!(g_lag >= crit)) break;
             }

@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("bin_seconds", ctypes.c_double), ("delta", ctypes.c_int32),
         ("n_bins", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("free_mode", ctypes.c_int32), ("lane_change", ctypes.c_int32),
+        ("eps_a", ctypes.c_float), ("eps_b", ctypes.c_float),
     ]
 
 
@@ -50,7 +51,7 @@ class Counters(ctypes.Structure):
 DEFAULT_PARAMS = dict(dt=0.5, a=1.0, b=1.5, s0=2.0, T=1.5, veh_len=5.0, x0=100.0,
                       g_a=2.0, g_b=2.0, alpha_i=1.0, alpha_a=1.0, alpha_b=1.0,
                       bin_seconds=300.0, delta=4, n_bins=12, seed=0x5EED,
-                      free_mode=0, lane_change=1)
+                      free_mode=0, lane_change=1, eps_a=0.0, eps_b=0.0)
 
 # exported symbol -> (argtypes, restype)
 _vp = ctypes.c_void_p

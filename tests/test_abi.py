@@ -35,8 +35,9 @@ def test_binding_covers_only_declared_symbols():
 
 
 def test_params_struct_matches_header_layout():
-    # float x12, double, int32 x2, uint64, int32 x2
-    assert ctypes.sizeof(lpsim.Params) == 12 * 4 + 8 + 2 * 4 + 8 + 2 * 4
+    # float x12, double, int32 x2, uint64, int32 x2, float x2
+    assert ctypes.sizeof(lpsim.Params) == 12 * 4 + 8 + 2 * 4 + 8 + 2 * 4 + 2 * 4
+    assert lpsim.Params.eps_b.offset == 84
     assert ctypes.sizeof(lpsim.Counters) == 12 * 8
 
 
@@ -47,6 +48,9 @@ def test_invalid_params_rejected_without_gpu():
     assert lib.lpsim_create(ctypes.byref(bad), ctypes.byref(h)) == lpsim.EINVAL
     bad = lpsim.Params(**dict(lpsim.DEFAULT_PARAMS, bin_seconds=0.7))
     assert lib.lpsim_create(ctypes.byref(bad), ctypes.byref(h)) == lpsim.EINVAL
+    for eps in (dict(eps_a=-1.0), dict(eps_b=101.0), dict(eps_a=float("nan"))):
+        bad = lpsim.Params(**dict(lpsim.DEFAULT_PARAMS, **eps))
+        assert lib.lpsim_create(ctypes.byref(bad), ctypes.byref(h)) == lpsim.EINVAL
     assert lib.lpsim_last_error(None) == b""
 
 

@@ -215,3 +215,28 @@ def test_autotune_keeps_state(Sim):
     assert_same_state(a.vehicles(), b.vehicles(), "autotuned")
     assert_same_stats(a.edge_stats(), b.edge_stats(), "autotuned")
     assert_same_counters(a.counters(), b.counters(), "autotuned")
+
+
+@pytest.mark.parametrize("eps_a,eps_b,lanes", [(1.0, 0.0, 2), (0.5, 3.0, 3), (4.0, 4.0, 3)])
+def test_random_gap_terms(Sim, eps_a, eps_b, lanes):
+    case("random gap terms", eps_a, eps_b, "lanes", lanes)
+    inst = synth.grid_instance(seed=90 + lanes, side=4, n_trips=700, depart_window=150,
+                               len_lo=20, len_hi=90, lanes=lanes)
+    params = dict(eps_a=eps_a, eps_b=eps_b, seed=1234, n_bins=6, bin_seconds=60.0)
+    gpu, ref = run_pair(Sim, inst, 600, 1, params=params)
+    assert ref.counters()["lc_accepts"] > 0
+
+
+def test_random_gap_terms_batch(Sim):
+    case("random gap terms in a batch of 3 (scenario seeds)")
+    insts = [synth.grid_instance(seed=95 + s, side=4, n_trips=400, depart_window=150,
+                                 len_lo=20, len_hi=90, lanes=3) for s in range(3)]
+    seeds = [11, 22, 33]
+    bat = Sim(eps_a=2.0, eps_b=1.0).load_batch(insts, seeds=seeds)
+    bat.step(600)
+    vb = bat.vehicles()
+    for s, inst in enumerate(insts):
+        t0, t1 = bat.trip_off[s], bat.trip_off[s + 1]
+        ref = oracle.OracleSim(eps_a=2.0, eps_b=1.0, seed=seeds[s]).load(inst)
+        ref.step(600)
+        assert_same_state({k: vb[k][t0:t1] for k in vb}, ref.vehicles(), f"scenario {s}")
