@@ -133,6 +133,10 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape first")
     ap.add_argument("--signals", action="store_true",
                     help="fixed-time two-phase signals at every node with 3+ approaches on both axes")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the surrogate perceptron leg")
+    ap.add_argument("--mlp-only", action="store_true", help="only run the surrogate perceptron leg")
+    ap.add_argument("--mlp-samples", type=int, default=2_200_000,
+                    help="inference batch of the perceptron leg (550k edges x 4 one-hour windows)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM traffic counters")
     args = ap.parse_args()
@@ -155,6 +159,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "launches": 5}), flush=True)
+        return
+    if args.mlp_only:
+        print(json.dumps({"surrogate_mlp": run_mlp(args.mlp_samples, 8192)}), flush=True)
         return
     t = time.perf_counter()
     inst, n_bins = make_workload(args.workload)
@@ -281,6 +288,9 @@ def main():
         out["dominant_kernel"] = dom
         log("kernel times:", json.dumps(out["kernel_ms"]))
 
+    if not args.no_mlp:
+        out["surrogate_mlp"] = run_mlp(args.mlp_samples, 8192)
+        log("surrogate perceptron:", json.dumps(out["surrogate_mlp"]))
     if not args.no_cpu_baseline and not batch:
         out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget, plan)
         log("cpu baseline:", json.dumps(out["cpu_baseline"]))
@@ -289,6 +299,64 @@ def main():
         out["assignment"] = run_assignment(a_inst, args.assign)
         out["assignment"]["workload"] = a_inst.name
     print(json.dumps(out), flush=True)
+
+
+# perceptron FLOPs per sample: forward over the four layers as computed (16
+# outputs); backward = weight gradients of all four layers + data gradients of
+# layers 2..4 (the input needs none)
+MLP_DIMS = ((32, 256), (256, 256), (256, 256), (256, 16))
+MLP_FWD_FLOP = sum(2 * i * o for i, o in MLP_DIMS)
+MLP_BWD_FLOP = MLP_FWD_FLOP + sum(2 * i * o for i, o in MLP_DIMS[1:])
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_mlp(n_fwd, n_train, reps=10):
+    """Time the surrogate perceptron's MFMA kernels with HIP events on the
+    stream they run on: the forward over an inference batch (every edge and
+    one-hour window of the regional network), and the backward over a training
+    batch and over the inference batch."""
+    import torch
+    from paper_2406_08496_amd.surrogate import EdgeMLP
+
+    net = EdgeMLP(seed=0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def entry(flop, ms):
+        tf = flop / (ms / 1e3) / 1e12
+        return {"ms": ms, "tflops": tf, "frac": tf / BF16_PEAK_TFLOPS}
+
+    out = {"bound": "mfma", "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "dtype": "bf16 operands, f32 accumulation",
+           "flop_per_sample": {"forward": MLP_FWD_FLOP, "backward": MLP_BWD_FLOP}}
+    x = torch.randn((n_fwd, 32), generator=g, device="cuda").to(torch.bfloat16)
+    out["forward"] = dict(entry(MLP_FWD_FLOP * n_fwd, timed(lambda: net.forward(x))), samples=n_fwd)
+    for name, n in (("backward_train_batch", n_train), ("backward", n_fwd)):
+        xb = x[:n].contiguous()
+        tgt = torch.randn((n, 16), generator=g, device="cuda")
+        y, hs = net.forward(xb, keep=True)
+        dz = torch.empty((n, 16), dtype=torch.bfloat16, device="cuda")
+        lib = net.lib
+        import ctypes
+        rc = lib.lpsim_mlp_loss_grad(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(tgt.data_ptr()), None, n,
+                                     ctypes.c_float(1.0 / (n * 16)), ctypes.c_void_p(dz.data_ptr()), None,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if rc:
+            raise RuntimeError(f"mlp loss gradient failed: {rc}")
+        out[name] = dict(entry(MLP_BWD_FLOP * n, timed(lambda: net.backward(xb, hs, dz))), samples=n)
+        del y, hs, dz, tgt, xb
+    return out
 
 
 def run_assignment(inst, n_iter):

@@ -130,14 +130,19 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
 // [K][N] ("in x out") so that the contraction over N is contiguous.
 // NC = contraction width padded to a multiple of 32.
 
+// rows per tile of the data-gradient kernel: its accumulators take TMD / 4
+// f32x4 per wave, which sets its occupancy (32 rows: 5 waves per SIMD,
+// faster than 64 or 128 rows)
+constexpr int TMD = 32;
+
 template <int N, int K>
 __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpBwdDataArgs a) {
     constexpr int NC = (N + 31) / 32 * 32;
     constexpr int LDZ = NC + 8;
-    constexpr int RB = TM / 16, CB = K / 16 / 4;
-    __shared__ __attribute__((aligned(16))) uint16_t zs[TM * LDZ];
-    const int64_t row0 = (int64_t)blockIdx.x * TM;
-    for (int c = threadIdx.x; c < TM * NC / 8; c += blockDim.x) {
+    constexpr int RB = TMD / 16, CB = K / 16 / 4;
+    __shared__ __attribute__((aligned(16))) uint16_t zs[TMD * LDZ];
+    const int64_t row0 = (int64_t)blockIdx.x * TMD;
+    for (int c = threadIdx.x; c < TMD * NC / 8; c += blockDim.x) {
         const int r = c / (NC / 8), q = (c % (NC / 8)) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (row0 + r < a.n && q < N) v = *reinterpret_cast<const uint4 *>(a.dz + (size_t)(row0 + r) * N + q);
@@ -146,23 +151,33 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpBwdDataArgs a) {
     __syncthreads();
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r16 = l & 15, kq = (l >> 4) * 8;
+    // the loops over the accumulator tiles are unrolled so that acc stays in
+    // registers (a rolled loop indexes it dynamically and puts it in scratch)
     f32x4 acc[RB][CB];
+#pragma unroll
     for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < NC; k0 += 32) {
         bf16x8 b[CB];
+#pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             const int col = (w * CB + cb) * 16 + r16;
             b[cb] = (k0 + kq < N) ? frag(a.w + (size_t)col * N + k0 + kq) : zero_frag();
         }
+#pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const bf16x8 av = frag(zs + (rb * 16 + r16) * LDZ + k0 + kq);
+#pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(av, b[cb], acc[rb][cb]);
         }
     }
+#pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         const int col = (w * CB + cb) * 16 + r16;
+#pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t row = row0 + rb * 16 + (l >> 4) * 4 + i;
                 if (row >= a.n) continue;
@@ -175,17 +190,28 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpBwdDataArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// rows per staging chunk of the weight-gradient kernel (a multiple of 32)
+constexpr int WG_ROWS = 32;
+
 // backward, weight part: partial dwt[n][k] = sum over a batch slice of
-// dz[m][n] * h[m][k], and partial db[n] = sum dz[m][n].  Chunks of 32 rows
-// are staged transposed in LDS so both operands are contiguous along m.
-// Block tile: 64 (n) x 64 (k); each wave owns one n block and four k blocks.
+// dz[m][n] * h[m][k], and partial db[n] = sum dz[m][n].  Chunks of WG_ROWS
+// rows are read with 16-byte loads and stored transposed in LDS, so both MFMA
+// operands are contiguous along m; the next chunk is loaded into registers
+// while the current one is multiplied.  Block tile: TN (n) x TK (k); its
+// 16 x 16 output blocks are dealt evenly to the four waves, and each output
+// element is summed by one MFMA chain in chunk order.
 
 template <int N, int K>
 __global__ __launch_bounds__(256) void k_mlp_bwd_weight(MlpBwdWeightArgs a) {
     constexpr int TN = N < 64 ? N : 64, TK = K < 64 ? K : 64;
-    constexpr int LT = 32 + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t pt[64 * LT];  // dz^T tile [n][m]
-    __shared__ __attribute__((aligned(16))) uint16_t qt[64 * LT];  // h^T tile [k][m]
+    constexpr int MC = WG_ROWS, LT = MC + 8;
+    static_assert(MC % 32 == 0, "chunks of whole MFMA steps");
+    constexpr int NB = TN / 16, KB = TK / 16, PER_WAVE = NB * KB / 4;
+    static_assert(NB * KB % 4 == 0 && PER_WAVE <= 4, "tile must split over four waves");
+    constexpr int VP = MC * TN / 8, VQ = MC * TK / 8;  // 16-byte vectors per chunk
+    constexpr int NVP = (VP + 255) / 256, NVQ = (VQ + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t pt[TN * LT];  // dz^T tile [n][m]
+    __shared__ __attribute__((aligned(16))) uint16_t qt[TK * LT];  // h^T tile [k][m]
     constexpr int n_tiles_k = K / TK;
     const int tile = blockIdx.x;
     const int nt = tile / n_tiles_k, kt = tile % n_tiles_k;
@@ -193,43 +219,69 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_weight(MlpBwdWeightArgs a) {
     const int split = blockIdx.y, n_split = gridDim.y;
     const int64_t per = ((a.n + n_split - 1) / n_split + 31) / 32 * 32;
     const int64_t m_lo = per * split, m_hi = m_lo + per < a.n ? m_lo + per : a.n;
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x;
+    const int l = t & 63, w = t >> 6;
     const int r16 = l & 15, mq = (l >> 4) * 8;
-    constexpr int NB = TN / 16, KB = TK / 16;
-    const bool active_wave = w < NB;
-    f32x4 acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 vp[NVP], vq[NVQ];
+    auto load = [&](int64_t m0) {
+#pragma unroll
+        for (int u = 0; u < NVP; ++u) {
+            const int v = t + 256 * u, m = v / (TN / 8), c = (v % (TN / 8)) * 8;
+            vp[u] = make_uint4(0, 0, 0, 0);
+            if (v < VP && m0 + m < m_hi) vp[u] = *reinterpret_cast<const uint4 *>(a.dz + (size_t)(m0 + m) * N + n0 + c);
+        }
+#pragma unroll
+        for (int u = 0; u < NVQ; ++u) {
+            const int v = t + 256 * u, m = v / (TK / 8), c = (v % (TK / 8)) * 8;
+            vq[u] = make_uint4(0, 0, 0, 0);
+            if (v < VQ && m0 + m < m_hi) vq[u] = *reinterpret_cast<const uint4 *>(a.h + (size_t)(m0 + m) * K + k0 + c);
+        }
+    };
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float dbias = 0.f;
-    for (int64_t m0 = m_lo; m0 < m_hi; m0 += 32) {
+    if (m_lo < m_hi) load(m_lo);
+    for (int64_t m0 = m_lo; m0 < m_hi; m0 += MC) {
+        __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+        for (int u = 0; u < NVP; ++u) {
+            const int v = t + 256 * u, m = v / (TN / 8), c = (v % (TN / 8)) * 8;
+            const uint32_t wv[4] = {vp[u].x, vp[u].y, vp[u].z, vp[u].w};
+            if (v < VP)
+                for (int j = 0; j < 8; ++j) pt[(c + j) * LT + m] = (uint16_t)(wv[j >> 1] >> (16 * (j & 1)));
+        }
+#pragma unroll
+        for (int u = 0; u < NVQ; ++u) {
+            const int v = t + 256 * u, m = v / (TK / 8), c = (v % (TK / 8)) * 8;
+            const uint32_t wv[4] = {vq[u].x, vq[u].y, vq[u].z, vq[u].w};
+            if (v < VQ)
+                for (int j = 0; j < 8; ++j) qt[(c + j) * LT + m] = (uint16_t)(wv[j >> 1] >> (16 * (j & 1)));
+        }
         __syncthreads();
-        // stage transposed: thread t copies element (m, n) / (m, k)
-        for (int c = threadIdx.x; c < 32 * TN; c += blockDim.x) {
-            const int m = c / TN, nn = c % TN;
-            const uint16_t v = (m0 + m < m_hi) ? a.dz[(size_t)(m0 + m) * N + n0 + nn] : (uint16_t)0;
-            pt[nn * LT + m] = v;
-        }
-        for (int c = threadIdx.x; c < 32 * TK; c += blockDim.x) {
-            const int m = c / TK, kk = c % TK;
-            const uint16_t v = (m0 + m < m_hi) ? a.h[(size_t)(m0 + m) * K + k0 + kk] : (uint16_t)0;
-            qt[kk * LT + m] = v;
-        }
-        __syncthreads();
-        if (active_wave) {
-            const bf16x8 p = frag(pt + (w * 16 + r16) * LT + mq);
-            for (int j = 0; j < KB; ++j) acc[j] = mfma(p, frag(qt + (j * 16 + r16) * LT + mq), acc[j]);
-        }
-        if (kt == 0 && threadIdx.x < TN)
-            for (int m = 0; m < 32; ++m) dbias += bf2f(pt[threadIdx.x * LT + m]);
+        if (m0 + MC < m_hi) load(m0 + MC);
+        // 32-row MFMA steps in increasing m: each element's sum keeps the row order
+#pragma unroll
+        for (int ms = 0; ms < MC; ms += 32)
+#pragma unroll
+            for (int j = 0; j < PER_WAVE; ++j) {
+                const int b = w * PER_WAVE + j, nb = b / KB, kb = b % KB;
+                acc[j] = mfma(frag(pt + (nb * 16 + r16) * LT + ms + mq), frag(qt + (kb * 16 + r16) * LT + ms + mq),
+                              acc[j]);
+            }
+        if (kt == 0 && t < TN)
+            for (int m = 0; m < MC; ++m) dbias += bf2f(pt[t * LT + m]);
     }
     float *part = a.ws + (size_t)split * (N * K + N);
-    if (active_wave) {
-        for (int j = 0; j < KB; ++j)
-            for (int i = 0; i < 4; ++i) {
-                const int nn = n0 + w * 16 + (l >> 4) * 4 + i, kk = k0 + j * 16 + r16;
-                part[(size_t)nn * K + kk] = acc[j][i];
-            }
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) {
+        const int b = w * PER_WAVE + j, nb = b / KB, kb = b % KB;
+        for (int i = 0; i < 4; ++i) {
+            const int nn = n0 + nb * 16 + (l >> 4) * 4 + i, kk = k0 + kb * 16 + r16;
+            part[(size_t)nn * K + kk] = acc[j][i];
+        }
     }
-    if (kt == 0 && threadIdx.x < TN) part[N * K + n0 + threadIdx.x] = dbias;
+    if (kt == 0 && t < TN) part[N * K + n0 + t] = dbias;
 }
 
 // deterministic sum of the split partials
@@ -297,7 +349,7 @@ hipError_t launch_fwd(const MlpFwdArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_bwd_data(int layer, const MlpBwdDataArgs &a, hipStream_t s) {
-    const unsigned g = (unsigned)((a.n + TM - 1) / TM);
+    const unsigned g = (unsigned)((a.n + TMD - 1) / TMD);
     if (!g) return hipSuccess;
     if (layer == 3) hipLaunchKernelGGL((k_mlp_bwd_data<OUT, HID>), dim3(g), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_mlp_bwd_data<HID, HID>), dim3(g), dim3(256), 0, s, a);

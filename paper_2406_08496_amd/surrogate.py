@@ -40,11 +40,13 @@ def _stream():
 class EdgeMLP:
     """Binary32 master weights, bfloat16 copies in both layouts, Adam state."""
 
-    def __init__(self, wt=None, b=None, seed=0, device="cuda", n_split=8):
+    def __init__(self, wt=None, b=None, seed=0, device="cuda", n_split=None):
         import torch
 
         self.torch = torch
         self.device = device
+        # batch slices of the weight-gradient kernels: fixed if given, else
+        # one per 128 rows up to 128 (the result depends only on the count)
         self.n_split = n_split
         if wt is None:
             rng = np.random.default_rng(seed)
@@ -109,17 +111,21 @@ class EdgeMLP:
         self.backward(x, hs, dz)
         return loss, y
 
+    def splits(self, n):
+        return self.n_split if self.n_split else max(1, min(128, (n + 127) // 128))
+
     def backward(self, x, hs, dz):
         torch = self.torch
         n = x.shape[0]
-        nbytes = self.lib.lpsim_mlp_workspace_bytes(self.n_split)
+        n_split = self.splits(n)
+        nbytes = self.lib.lpsim_mlp_workspace_bytes(n_split)
         if self._ws is None or self._ws.numel() * 4 < nbytes:
             self._ws = torch.empty(nbytes // 4, dtype=torch.float32, device=self.device)
         scratch = torch.empty((2, n, HID), dtype=torch.bfloat16, device=self.device)
         _check(self.lib.lpsim_mlp_backward(ctypes.c_void_p(x.data_ptr()), _ptrs(hs), ctypes.c_void_p(dz.data_ptr()),
                                            _ptrs(self.w_bf), _ptrs(self.g_w), _ptrs(self.g_b),
                                            ctypes.c_void_p(scratch.data_ptr()), ctypes.c_void_p(self._ws.data_ptr()),
-                                           self.n_split, n, _stream()), "mlp backward")
+                                           n_split, n, _stream()), "mlp backward")
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1

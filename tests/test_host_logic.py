@@ -74,3 +74,12 @@ def test_mlp_entry_points_validate_arguments():
     assert lib.lpsim_mlp_shape(ctypes.byref(i), ctypes.byref(h), ctypes.byref(o)) == 0
     assert (i.value, h.value, o.value) == (32, 256, 16)
     assert lib.lpsim_mlp_workspace_bytes(8) > 0
+
+
+def test_bench_mlp_flop_model():
+    import bench
+
+    # 2 * (32*256 + 256*256 + 256*256 + 256*16) forward; backward adds the
+    # data gradients of layers 2..4
+    assert bench.MLP_FWD_FLOP == 286_720
+    assert bench.MLP_BWD_FLOP == 286_720 + 2 * (256 * 256 + 256 * 256 + 256 * 16)
