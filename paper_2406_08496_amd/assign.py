@@ -340,9 +340,14 @@ class Assignment:
                 M = torch.cat([b[2] for b in buf])
                 g = torch.Generator(device=dev)
                 g.manual_seed(n)
-                for _ in range(train_steps):
-                    idx = torch.randint(0, X.shape[0], (min(batch, X.shape[0]),), device=dev, generator=g)
-                    net.train_step(X[idx].contiguous(), Y[idx].contiguous(), M[idx].contiguous(), lr=lr)
+                # the batches drawn as one per step, then every batch's mask
+                # count read back at once (one device sync, not one per step)
+                idxs = [torch.randint(0, X.shape[0], (min(batch, X.shape[0]),), device=dev, generator=g)
+                        for _ in range(train_steps)]
+                counts = torch.stack([M[idx].sum() for idx in idxs]).tolist() if idxs else []
+                for idx, cnt in zip(idxs, counts):
+                    net.train_step(X[idx].contiguous(), Y[idx].contiguous(), M[idx].contiguous(), lr=lr,
+                                   count=int(cnt))
                 torch.cuda.synchronize()
                 self._add("train", time.perf_counter() - ts)
                 rec["samples"] = int(X.shape[0])

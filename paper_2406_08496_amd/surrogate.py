@@ -95,14 +95,16 @@ class EdgeMLP:
         return (y, hs) if keep else y
 
     # -- training ------------------------------------------------------------
-    def gradients(self, x, target, mask=None):
-        """Loss (masked MSE) and gradients into self.g_w / self.g_b."""
+    def gradients(self, x, target, mask=None, count=None):
+        """Loss (masked MSE) and gradients into self.g_w / self.g_b.  `count`
+        (the number of set mask entries) may be given to spare a device sync."""
         torch = self.torch
         n = x.shape[0]
         y, hs = self.forward(x, keep=True)
         dz = torch.empty((n, OUT), dtype=torch.bfloat16, device=self.device)
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
-        count = int(mask.sum().item()) if mask is not None else n * OUT
+        if count is None:
+            count = int(mask.sum().item()) if mask is not None else n * OUT
         inv = 1.0 / max(count, 1)
         mptr = ctypes.c_void_p(mask.data_ptr()) if mask is not None else None
         _check(self.lib.lpsim_mlp_loss_grad(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(target.data_ptr()),
@@ -141,7 +143,7 @@ class EdgeMLP:
                 ctypes.c_void_p(self.m_b[l].data_ptr()), ctypes.c_void_p(self.v_b[l].data_ptr()),
                 1, o, f(lr), f(beta1), f(beta2), f(eps), self.t, _stream()), "mlp adam")
 
-    def train_step(self, x, target, mask=None, lr=1e-3):
-        loss, _ = self.gradients(x, target, mask)
+    def train_step(self, x, target, mask=None, lr=1e-3, count=None):
+        loss, _ = self.gradients(x, target, mask, count)
         self.adam_step(lr=lr)
         return loss
