@@ -25,12 +25,14 @@ struct lpsim_router {
     std::vector<int32_t> src, dst;
     std::vector<int64_t> in_off;   // incoming edges per node (CSR)
     std::vector<int32_t> in_edges;
+    std::vector<int32_t> in_src;   // upstream node of each in_edges entry
+    std::vector<double> in_cost;   // cost of each in_edges entry (this solve)
     // last solve
     std::vector<int32_t> dests;      // distinct destination nodes
     std::vector<int32_t> dest_idx;   // per trip
     std::vector<int32_t> origin;     // per trip
     std::vector<int32_t> next_edge;  // [dest][node]
-    std::vector<int32_t> len;        // per trip, new route length
+    std::vector<int32_t> len;        // per trip, new route length (trips taking one)
     bool solved = false;
 };
 
@@ -58,11 +60,13 @@ void tree_to(const lpsim_router &r, const double *cost, int32_t target, int32_t 
         const int32_t y = it.node;
         if (done[y]) continue;
         done[y] = 1;
+        // incoming edges with their upstream node and cost stored side by
+        // side: sequential reads instead of two gathers per edge
         for (int64_t j = r.in_off[y]; j < r.in_off[y + 1]; ++j) {
             const int32_t e = r.in_edges[j];
-            const int32_t x = r.src[e];
+            const int32_t x = r.in_src[j];
             if (done[x]) continue;
-            const double cand = dist[y] + cost[e];
+            const double cand = dist[y] + r.in_cost[j];
             if (cand < dist[x] || (cand == dist[x] && e < nx[x])) {
                 dist[x] = cand;
                 nx[x] = e;
@@ -114,6 +118,8 @@ int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src
         r->in_edges.resize((size_t)n_edges);
         std::vector<int64_t> pos(r->in_off.begin(), r->in_off.end() - 1);
         for (int32_t e = 0; e < n_edges; ++e) r->in_edges[(size_t)pos[(size_t)dst[e]]++] = e;
+        r->in_src.resize((size_t)n_edges);
+        for (size_t j = 0; j < r->in_edges.size(); ++j) r->in_src[j] = src[r->in_edges[j]];
     } catch (...) {
         delete r;
         return LPSIM_ENOMEM;
@@ -148,6 +154,8 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
         }
         const int32_t nd = (int32_t)r->dests.size();
         r->next_edge.assign((size_t)nd * r->n_nodes, -1);
+        r->in_cost.resize(r->in_edges.size());
+        for (size_t j = 0; j < r->in_edges.size(); ++j) r->in_cost[j] = cost[r->in_edges[j]];
         const int32_t nw = std::max(1, std::min(r->n_threads, nd));
         std::vector<std::vector<double>> dist(nw, std::vector<double>((size_t)r->n_nodes));
         std::vector<std::vector<uint8_t>> done(nw, std::vector<uint8_t>((size_t)r->n_nodes));
@@ -165,29 +173,13 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
         for (int32_t w = 1; w < nw; ++w) pool.emplace_back(worker, w);
         worker(0);
         for (auto &t : pool) t.join();
-        // route lengths
+        // every destination reachable: the origin has an edge toward it (a
+        // shortest-path tree then leads there); route lengths are measured
+        // by lpsim_router_fill for the trips that take a new route
+        for (int64_t i = 0; i < n_trips; ++i)
+            if (r->next_edge[(size_t)r->dest_idx[(size_t)i] * r->n_nodes + (size_t)r->origin[(size_t)i]] < 0)
+                return LPSIM_EINVAL;
         r->len.assign((size_t)n_trips, 0);
-        std::atomic<int> bad{0};
-        const int64_t chunk = 65536;
-        const int32_t n_chunks = (int32_t)((n_trips + chunk - 1) / chunk);
-        parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
-            for (int64_t i = ci * chunk; i < std::min<int64_t>(n_trips, (ci + 1) * chunk); ++i) {
-                const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
-                const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
-                int32_t u = r->origin[(size_t)i], l = 0;
-                while (u != t) {
-                    const int32_t e = nx[u];
-                    if (e < 0 || l > r->n_nodes) {
-                        bad = 1;
-                        break;
-                    }
-                    u = r->dst[(size_t)e];
-                    ++l;
-                }
-                r->len[(size_t)i] = l;
-            }
-        });
-        if (bad) return LPSIM_EINVAL;  // some destination unreachable
     } catch (...) {
         return LPSIM_ENOMEM;
     }
@@ -200,6 +192,24 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
     if (!r || !r->solved || !out_off) return LPSIM_ESTATE;
     const int64_t n = (int64_t)r->len.size();
     if (take_new && (!old_off || !old_edges)) return LPSIM_EINVAL;
+    const int64_t chunk = 65536;
+    const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
+    if (!out_edges) {
+        // lengths of the new routes (walks down the destination's tree)
+        parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
+            for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
+                if (take_new && !take_new[i]) continue;
+                const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+                const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
+                int32_t u = r->origin[(size_t)i], l = 0;
+                while (u != t && l <= r->n_nodes) {
+                    u = r->dst[(size_t)nx[u]];
+                    ++l;
+                }
+                r->len[(size_t)i] = l;
+            }
+        });
+    }
     out_off[0] = 0;
     for (int64_t i = 0; i < n; ++i) {
         const bool nw = !take_new || take_new[i];
@@ -207,8 +217,6 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
         out_off[i + 1] = out_off[i] + l;
     }
     if (!out_edges) return LPSIM_OK;
-    const int64_t chunk = 65536;
-    const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
     parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
         for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
             int32_t *o = out_edges + out_off[i];
