@@ -190,3 +190,20 @@ def test_restore_follows_current_plan(Sim):
         ref.step(20)
         assert_same_state(gpu.vehicles(), ref.vehicles(), f"step {k + 20}")
     assert_same_stats(gpu.edge_stats(), ref.edge_stats())
+
+
+def test_signals_with_random_gap_terms(Sim):
+    case("signalised 5x5 grid, 3 lanes, random gap terms, every step")
+    inst = synth.grid_instance(seed=77, side=5, n_trips=1200, depart_window=300, len_lo=25, len_hi=110, lanes=3)
+    plan = synth.signal_plan(inst, seed=77, green_s=15.0, allred_s=3.0)
+    params = dict(eps_a=1.5, eps_b=2.5, seed=4242, n_bins=6, bin_seconds=60.0)
+    gpu, ref = pair(Sim, inst, plan, params=params, launch=(256, 64, 16))
+    for k in range(1, 801):
+        gpu.step(1)
+        ref.step(1)
+        if k % 2 == 0:
+            assert_same_state(gpu.vehicles(), ref.vehicles(), f"step {k}")
+    assert_same_stats(gpu.edge_stats(), ref.edge_stats())
+    assert_same_counters(gpu.counters(), ref.counters())
+    c = ref.counters()
+    assert c["lc_accepts"] > 0 and c["claims_lost"] > 0
