@@ -83,3 +83,29 @@ def test_bench_mlp_flop_model():
     # data gradients of layers 2..4
     assert bench.MLP_FWD_FLOP == 286_720
     assert bench.MLP_BWD_FLOP == 286_720 + 2 * (256 * 256 + 256 * 256 + 256 * 16)
+
+
+def test_signal_plan_generator():
+    """The synthetic plan is a valid input: signals only at nodes with 3+
+    approaches on both axes, every approach of such a node served in the
+    phase of its axis, offsets inside the cycle, nothing elsewhere."""
+    import numpy as np
+
+    from paper_2406_08496_amd import synth
+
+    inst = synth.grid_instance(seed=3, side=6, n_trips=10)
+    p = synth.signal_plan(inst, seed=1, green_s=40.0, allred_s=5.0)
+    indeg = np.bincount(inst.dst, minlength=inst.n_nodes)
+    sig = p.n_phases > 0
+    assert sig.any() and np.all(indeg[sig] >= 3)
+    assert np.all(p.n_phases[sig] == 2) and np.all(p.green[sig] == 80) and np.all(p.allred[sig] == 10)
+    cycle = 2 * (p.green + p.allred)
+    assert np.all((p.offset[sig] >= 0) & (p.offset[sig] < cycle[sig]))
+    served = p.edge_phase >= 0
+    assert np.array_equal(served, sig[inst.dst])
+    d = inst.node_xy[inst.dst] - inst.node_xy[inst.src]
+    axis = np.where(np.abs(d[:, 0]) >= np.abs(d[:, 1]), 0, 1)
+    assert np.array_equal(p.edge_phase[served], axis[served])
+    # both phases present at every signalised node
+    for n in np.nonzero(sig)[0]:
+        assert set(p.edge_phase[inst.dst == n]) == {0, 1}
