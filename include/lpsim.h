@@ -107,11 +107,13 @@ typedef struct {
     int64_t watchdog;      /* consecutive steps with vehicles but no entry/exit */
     int64_t scan_bytes;    /* bytes the move launch reads beyond each vehicle's
                               28-byte state: lane-map cells scanned, next-edge entry
-                              windows, entry requests, and the departure requests' reads */
+                              windows, signal words at a stop line (edge id and word,
+                              12), entry requests, and the departure requests' reads */
 } lpsim_counters;
 
 /* Create a context.  `p` (host) is copied and validated: every length, time
- * and rate > 0 (gaps and alphas >= 0), delta == 4, bin_seconds/dt integral.
+ * and rate > 0 (gaps and alphas >= 0, eps_a and eps_b in 0..100), delta == 4,
+ * bin_seconds/dt integral.
  * Errors: EINVAL, ENOMEM, EDEVICE (no usable GPU). */
 int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out);
 
