@@ -9,7 +9,7 @@ namespace lpsim_mlp {
 constexpr int IN = 32;    // input features (padded)
 constexpr int HID = 256;  // hidden width, three hidden layers
 constexpr int OUT = 16;   // outputs (padded)
-constexpr int TM = 128;   // rows per workgroup in the row-tiled kernels
+constexpr int TM = 64;    // rows per workgroup of the forward (2 waves per SIMD; 128 rows gave 1)
 constexpr int LDX = IN + 8;    // LDS row pitch (bf16) of the input tile
 constexpr int LDH = HID + 8;   // LDS row pitch of a hidden tile (bank spread)
 
