@@ -48,8 +48,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # below); otherwise the bench reports null.  Commands and figures:
 # profiles/k_move_regional_hbm_traffic.md
 MOVE_TRAFFIC_WORKLOAD = "regional-225k-2.82M"
-MOVE_TRAFFIC = {"kernels_sha256": "19802b12eae75db41dbabb886f0187f1ea41a2b3891cdfc81e1a63180836ed1f",
-                "fetch_kib": 29219.49, "write_kib": 16418.02, "fetch_scale": 2.0, "write_scale": 1.0}
+MOVE_TRAFFIC = {"kernels_sha256": "5161b11eed9ab4a33091ed24691d63b4cc3fe7214637d890c7ba81ac54bb816d",
+                "fetch_kib": 29218.37, "write_kib": 16417.55, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def move_traffic_bytes(workload=MOVE_TRAFFIC_WORKLOAD):

@@ -753,10 +753,8 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
     Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
-    const uint32_t ncand_dep = ctl->n_wq + (dep_hi_of(d, k) - ctl->dep_done);
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
-    (void)ncand_dep;
     // a single scenario's draw seed and trip base, read once beside the control block
     const bool one_scen = d.n_scen == 1;
     uint64_t seed0 = 0;
@@ -896,11 +894,8 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d, uint32_t X, uint32_t G) 
         return;
     }
     const Ctrl *ctl = d.ctrl;
-    const int32_t k = ctl->k;
     const uint32_t n = ctl->n_slots;
-    const uint32_t ncand_dep = ctl->n_wq + (dep_hi_of(d, k) - ctl->dep_done);
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    (void)ncand_dep;
     uint64_t lo, hi;
     const uint32_t lb = logical_block(blockIdx.x - X, G);
     block_range(n, lb, G, lo, hi);
