@@ -194,8 +194,10 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
     if (take_new && (!old_off || !old_edges)) return LPSIM_EINVAL;
     const int64_t chunk = 65536;
     const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
-    if (!out_edges) {
-        // lengths of the new routes (walks down the destination's tree)
+    {
+        // lengths of the new routes (walks down the destination's tree);
+        // measured on every call, so a call that writes the edges without a
+        // sizing call first still gets its offsets right
         parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
             for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
                 if (take_new && !take_new[i]) continue;

@@ -98,3 +98,24 @@ def test_msa_switch_share():
         if prev is not None:
             assert not np.array_equal(s, prev)
         prev = s
+
+
+def test_fill_in_one_call():
+    """Writing the edges without a sizing call first gives the same routes
+    (the lengths are measured on every call)."""
+    inst = synth.grid_instance(seed=6, side=6, n_trips=400)
+    cost = (inst.length / inst.speed).astype(np.float64)
+    origin = np.ascontiguousarray(inst.meta["origin"], np.int32)
+    dest = np.ascontiguousarray(inst.meta["dest"], np.int32)
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=3)
+    take = (np.arange(inst.n_trips) % 3 == 0).astype(np.uint8)
+    old = (np.ascontiguousarray(inst.route_off, np.int64), np.ascontiguousarray(inst.route_edges, np.int32))
+    off2, edges2 = r.routes(cost * 1.7, origin, dest, old=old, take_new=take)
+    # a fresh solve, then one call with a buffer sized by the two-call result
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    c2 = np.ascontiguousarray(cost * 1.7)
+    assert r.lib.lpsim_router_solve(r._h, vp(c2), inst.n_trips, vp(origin), vp(dest)) == 0
+    off1 = np.zeros(inst.n_trips + 1, np.int64)
+    edges1 = np.zeros(len(edges2), np.int32)
+    assert r.lib.lpsim_router_fill(r._h, vp(old[0]), vp(old[1]), vp(take), vp(off1), vp(edges1)) == 0
+    assert np.array_equal(off1, off2) and np.array_equal(edges1, edges2)
