@@ -361,7 +361,8 @@ def run_mlp(n_fwd, n_train, reps=10):
 
 def run_assignment(inst, n_iter):
     """MSA with the full simulation every iteration vs surrogate-assisted MSA
-    (full simulation on iterations 1, 6, 11, ... and whenever the judge fails),
+    (full simulation on iterations 1, 6, 11, ... and whenever the last
+    simulation rejected the surrogate's estimate of its routes),
     same GPU; wall times include routing, simulation, loading and training.
     Agreement of the final edge travel times: flow-weighted mean relative
     difference, flow-weighted relative L2, and the relative difference of the
