@@ -40,28 +40,25 @@ HBM_PEAK_GBS = 8000.0
 #   slot state write: x, v, meta (12)
 MOVE_FIXED_BYTES = 12 + 16 + 12
 
-# HBM traffic of one k_move launch on this workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean over the 28,800
-# launches), each scaled by what the same counter reads for a plain 1 GiB
-# device copy (FETCH_SIZE reads half the copied bytes, WRITE_SIZE all of them).
-# Valid only for the workload and the kernel source it was taken on (sha256
-# below); otherwise the bench reports null.  Commands and figures:
-# profiles/k_move_regional_hbm_traffic.md
-MOVE_TRAFFIC_WORKLOAD = "regional-225k-2.82M"
-MOVE_TRAFFIC = {"kernels_sha256": "5161b11eed9ab4a33091ed24691d63b4cc3fe7214637d890c7ba81ac54bb816d",
-                "fetch_kib": 29218.37, "write_kib": 16417.55, "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM traffic of one k_move launch, from two rocprofv3 --pmc runs of the
+# benchmark command itself (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean
+# over the dispatches of the timed window), each scaled by what the same
+# counter reads for a plain device copy of known size.  A figure is reported
+# only for the workload and window it was counted on, and only while the
+# kernel source hashes to the value it was counted with; otherwise null.
+MOVE_TRAFFIC = {}
 
 
-def move_traffic_bytes(workload=MOVE_TRAFFIC_WORKLOAD):
+def move_traffic_bytes(workload, start, steps):
     import hashlib
 
-    if workload != MOVE_TRAFFIC_WORKLOAD:
+    t = MOVE_TRAFFIC.get((workload, start, steps))
+    if t is None:
         return None
     src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    t = MOVE_TRAFFIC
-    if t["kernels_sha256"] != sha or t["fetch_kib"] is None:
+    if t["kernels_sha256"] != sha:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
@@ -92,37 +89,102 @@ def make_workload(name):
 
 
 def cpu_baseline(inst, n_bins, budget_s, plan=None):
-    """The oracle as it is, single thread, from step 0 until the budget runs out."""
+    """The oracle as it is, on the host cores: the single-threaded build from
+    step 0 until `budget_s` runs out (whole 100-step blocks), then the
+    all-cores build (OpenMP, same results) over the same steps.  Returns the
+    entry and the number of steps of the sample."""
     import oracle
 
-    o = oracle.OracleSim(n_bins=n_bins).load(inst)
-    if plan is not None:
-        o.set_signals(plan)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s and steps < inst.n_steps:
-        o.step(100)
-        steps += 100
-    el = time.perf_counter() - t0
-    c = o.counters()
-    return {"value": c["vehicle_steps"] / el, "unit": "vehicle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"steps 0..{steps} of the same workload ({c['vehicle_steps']} vehicle-steps, "
-                      f"{el:.1f} s, single thread)"}
+    legs = {}
+    steps = None
+    for parallel in (False, True):
+        o = oracle.OracleSim(parallel=parallel, n_bins=n_bins).load(inst)
+        if plan is not None:
+            o.set_signals(plan)
+        t0 = time.perf_counter()
+        done = 0
+        while (done < steps) if steps is not None else (time.perf_counter() - t0 < budget_s
+                                                         and done < inst.n_steps):
+            o.step(100)
+            done += 100
+        el = time.perf_counter() - t0
+        steps = done
+        c = o.counters()
+        legs[parallel] = {"value": c["vehicle_steps"] / el, "cores": o.threads, "seconds": el,
+                          "vehicle_steps": c["vehicle_steps"]}
+        del o
+    par, one = legs[True], legs[False]
+    out = {"value": par["value"], "unit": "vehicle-steps/s", "cores": par["cores"], "kind": "oracle",
+           "sample": f"steps 0..{steps} of the same workload ({par['vehicle_steps']} vehicle-steps); "
+                     f"all-cores build {par['seconds']:.1f} s on {par['cores']} threads, "
+                     f"single-threaded build {one['seconds']:.1f} s",
+           "single_thread": {"value": one["value"], "cores": 1, "seconds": one["seconds"]}}
+    return out, steps
+
+
+def find_peak(sim, horizon, every=64):
+    """Step from the current state to the horizon and return the step (a
+    multiple of `every`) at which the most vehicles were on the road, with
+    that count and the counters at the horizon."""
+    best, best_k, k = -1, 0, 0
+    while k < horizon:
+        n = min(every, horizon - k)
+        sim.step(n)
+        k += n
+        a = sim.counters()["active"]
+        if a > best:
+            best, best_k = a, k
+    return best_k, best, sim.counters()
+
+
+def window_state(sim, n_trips):
+    """What the road looks like at the start of the timed window."""
+    v = sim.vehicles()
+    act = v["status"] == 1
+    n_act = int(act.sum())
+    stopped = int((act & (v["v"] == 0)).sum())
+    c = sim.counters()
+    return {"active": n_act, "stopped_share": stopped / max(n_act, 1),
+            "waiting": c["waiting"], "arrived_fraction": c["arrived"] / max(n_trips, 1)}
+
+
+CNT_DELTA = ("vehicle_steps", "transfers", "departures", "arrived", "claims_lost", "lc_attempts",
+             "lc_accepts", "scan_bytes")
+
+
+def delta(c1, c0):
+    return {k: c1[k] - c0[k] for k in CNT_DELTA}
+
+
+def step_bytes(d, look_ahead):
+    """Algorithmic bytes of whole steps from the counters of the steps: per
+    vehicle-step the state read (18: x, v, edge, lane, status, route index),
+    x and v written (8) and the map commit (2); what the move launch counts
+    into scan_bytes (cells scanned, entry windows near a stop line, entry
+    requests, departure requests); 16 per exit (statistics), 20 per
+    departure; two look-ahead windows per lane-change attempt."""
+    exits = d["transfers"] + d["arrived"]
+    return (28 * d["vehicle_steps"] + d["scan_bytes"] + 16 * exits + 20 * d["departures"]
+            + 2 * look_ahead * d["lc_attempts"])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: full horizon)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps; without it the whole horizon from step 0 is timed")
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--window-start", default=None,
+                    help="first timed step: 'peak' (the step with the most vehicles on the road, "
+                         "the default with --steps) or a step number (default 0 without --steps)")
     ap.add_argument("--repeat", type=int, default=3,
                     help="timed runs of the same steps from the same state; the median is reported")
     ap.add_argument("--workload", default="regional")
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--blocks", type=int, default=640)
     ap.add_argument("--graph-steps", type=int, default=64)
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of the single-threaded oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--assign", type=int, default=0,
@@ -184,8 +246,6 @@ def main():
         plan = (synth.concat_signal_plans([synth.signal_plan(i) for i in insts], insts) if batch
                 else synth.signal_plan(inst))
         name += "+signals"
-    K = args.steps if args.steps is not None else horizon
-    W = args.warmup
     log(f"workload {name}: {n_nodes} nodes, {n_edges} edges, {n_trips} trips, "
         f"{n_route} route entries; generated in {time.perf_counter() - t:.1f} s")
 
@@ -201,26 +261,48 @@ def main():
         log(f"signals at {plan.n_signals} nodes")
     log(f"loaded in {time.perf_counter() - t:.1f} s")
     stream = torch.cuda.current_stream()
+    snap0 = sim.save_state()
+
+    # the timed window: K steps from step P
+    full = args.steps is None
+    K = horizon if full else args.steps
+    ws = args.window_start if args.window_start is not None else ("0" if full else "peak")
+    horizon_info = None
+    if ws == "peak":
+        t = time.perf_counter()
+        peak_k, peak_active, ch = find_peak(sim, horizon)
+        P = min(peak_k, max(horizon - K, 0))
+        horizon_info = {"active_peak": peak_active, "active_peak_step": peak_k,
+                        "arrived_fraction": ch["arrived"] / n_trips, "vehicle_steps": ch["vehicle_steps"]}
+        log(f"most vehicles on the road: {peak_active} at step {peak_k} (found in "
+            f"{time.perf_counter() - t:.1f} s); horizon: arrived {ch['arrived']}/{n_trips}")
+        sim.restore_state(snap0)
+    else:
+        P = int(ws)
+    if P:
+        sim.step(P)
+    snapP = sim.save_state() if P else snap0
+    win = window_state(sim, n_trips)
+    c_start = sim.counters()
+    log(f"window: steps {P}..{P + K}; at its start {win['active']} vehicles on the road "
+        f"({100 * win['stopped_share']:.1f}% standing), {win['waiting']} trips waiting")
     tuned = None
     if args.autotune:
-        # tune on a loaded state (a third of the horizon in), then rewind
-        snap = sim.save_state()
-        sim.step(horizon // 3)
         tuned = sim.autotune(n_steps=64)
-        sim.restore_state(snap)
-        log(f"autotuned: block {tuned['block_size']}, blocks {tuned['blocks']}")
-        tuned = {"block": tuned["block_size"], "blocks": tuned["blocks"]}
-    # warm-up steps (graph capture, caches), then rewind to step 0
-    snap0 = sim.save_state()
+        log(f"autotuned on the window state: block {tuned['block_size']}, blocks {tuned['blocks']}")
+        tuned = {"block": tuned["block_size"], "blocks": tuned["blocks"],
+                 "trial_us_per_step": {f"{b}x{g}": round(u, 2) for (b, g), u in tuned["us_per_step"].items()}}
+    # warm-up steps (graph capture, caches), then rewind to the window start
+    W = args.warmup
     if W:
         sim.step(W, stream=stream)
         torch.cuda.synchronize()
-    sim.restore_state(snap0)
+    sim.restore_state(snapP)
 
     runs = []
     for r in range(max(1, args.repeat)):
         if r:
-            sim.restore_state(snap0)
+            sim.restore_state(snapP)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -230,14 +312,22 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         runs.append((ev0.elapsed_time(ev1), wall))
-        log(f"run {r}: {runs[-1][0]:.1f} ms")
+        log(f"run {r}: {runs[-1][0]:.2f} ms")
     ms, wall = sorted(runs)[len(runs) // 2]
-    c = sim.counters()
-    vsteps = c["vehicle_steps"]
+    c_end = sim.counters()
+    dw = delta(c_end, c_start)
+    vsteps = dw["vehicle_steps"]
     value = vsteps / (ms / 1e3)
-    log(f"timed {K} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), {vsteps} vehicle-steps, "
-        f"arrived {c['arrived']}/{n_trips}, active {c['active']}, watchdog {c['watchdog']}")
+    win["arrived_fraction_end"] = c_end["arrived"] / n_trips
+    win["mean_active"] = vsteps / K
+    log(f"timed {K} steps: {ms:.2f} ms (wall {wall * 1e3:.2f} ms), {vsteps} vehicle-steps, "
+        f"arrived {c_end['arrived']}/{n_trips}, active {c_end['active']}, watchdog {c_end['watchdog']}")
 
+    cfg = {"workload": name, "nodes": n_nodes, "edges": n_edges, "trips": n_trips, "dt": 0.5,
+           "horizon_steps": horizon, "window_start_step": P, "window_steps": K,
+           "block": tuned["block"] if tuned else args.block,
+           "blocks": tuned["blocks"] if tuned else args.blocks, "graph_steps": args.graph_steps,
+           "signalised_nodes": plan.n_signals if plan is not None else 0}
     out = {
         "metric": (f"vehicle-steps/sec, {len(insts)} batched scenarios" if batch else
                    f"vehicle-steps/sec at {n_trips / 1e6:.3g}M trips".replace("2.82M", "2.8M")),
@@ -252,36 +342,42 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded planar graph + gravity demand standing in for SF Bay / SFCTA)",
-        "config": {"workload": name, "nodes": n_nodes, "edges": n_edges,
-                   "trips": n_trips, "dt": 0.5, "horizon_steps": horizon,
-                   "block": tuned["block"] if tuned else args.block,
-                   "blocks": tuned["blocks"] if tuned else args.blocks, "graph_steps": args.graph_steps,
-                   "signalised_nodes": plan.n_signals if plan is not None else 0},
-        "trips_per_s": c["arrived"] / (ms / 1e3),
-        "arrived": c["arrived"],
+        "config": cfg,
+        "window": win,
+        "trips_per_s": (c_end["arrived"] - c_start["arrived"]) / (ms / 1e3),
         "vehicle_steps": vsteps,
-        "runs_ms": [round(x[0], 2) for x in runs],
+        "runs_ms": [round(x[0], 3) for x in runs],
     }
+    if horizon_info is not None:
+        out["horizon"] = horizon_info
+    if tuned:
+        out["autotune"] = tuned
 
     if not args.no_roofline:
-        # same K steps from the same state, kernels launched one by one with a
-        # HIP event pair around each on the work stream
-        sim.restore_state(snap0)
+        # the same K steps from the same state, kernels launched one by one
+        # with their dispatch timestamps taken by HIP events on the work stream
+        sim.restore_state(snapP)
+        c0 = sim.counters()
         sim.set_timing(True)
         sim.step(K, stream=stream)
         torch.cuda.synchronize()
         times = sim.kernel_times()
-        c2 = sim.counters()
+        d2 = delta(sim.counters(), c0)
         sim.set_timing(False)
         dom = max(times, key=lambda k: times[k][0])
-        alg_bytes = MOVE_FIXED_BYTES * c2["vehicle_steps"] + c2["scan_bytes"]
+        alg_bytes = MOVE_FIXED_BYTES * d2["vehicle_steps"] + d2["scan_bytes"]
         mv_ms, mv_n = times["move"]
         achieved = alg_bytes / (mv_ms / 1e3) / 1e9
+        traffic = move_traffic_bytes(name, P, K)
         out["roofline"] = {"bound": "hbm", "kernel": "k_move", "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": move_traffic_bytes(name),
+                           "traffic": traffic,
                            "bytes_per_launch": alg_bytes / max(mv_n, 1),
                            "avg_launch_us": mv_ms * 1e3 / max(mv_n, 1)}
+        sb = step_bytes(dw, sim.D)
+        step_gbs = sb / (ms / 1e3) / 1e9
+        out["step_roofline"] = {"bound": "hbm", "achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": step_gbs / HBM_PEAK_GBS, "bytes_per_step": sb / K}
         out["kernel_ms"] = {k: {"total_ms": v[0], "launches": v[1],
                                 "avg_us": (v[0] * 1e3 / v[1]) if v[1] else None}
                             for k, v in times.items()}
@@ -292,7 +388,20 @@ def main():
         out["surrogate_mlp"] = run_mlp(args.mlp_samples, 8192)
         log("surrogate perceptron:", json.dumps(out["surrogate_mlp"]))
     if not args.no_cpu_baseline and not batch:
-        out["cpu_baseline"] = cpu_baseline(inst, n_bins, args.cpu_budget, plan)
+        cb, s_steps = cpu_baseline(inst, n_bins, args.cpu_budget, plan)
+        # the GPU on exactly the oracle's sample, for the comparison
+        sim.restore_state(snap0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(s_steps, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        g_ms = e0.elapsed_time(e1)
+        g_vs = sim.counters()["vehicle_steps"]
+        cb["gpu_same_sample"] = {"value": g_vs / (g_ms / 1e3), "ms": g_ms,
+                                 "vs_all_cores": (g_vs / (g_ms / 1e3)) / cb["value"]}
+        out["cpu_baseline"] = cb
         log("cpu baseline:", json.dumps(out["cpu_baseline"]))
     if args.assign and not batch:
         a_inst = inst if args.assign_workload is None else make_workload(args.assign_workload)[0]

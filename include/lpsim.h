@@ -181,10 +181,16 @@ int32_t lpsim_batch_load(lpsim_ctx *ctx, int32_t n_scen, const int32_t *node_off
  *   hip_stream   a hipStream_t to order the work on, or NULL: then the call
  *                runs on an internal stream and returns after the work is done.
  * With a stream the call only enqueues; the caller synchronises the stream.
+ * A call on a different stream than the previous call is ordered after the
+ * work that call queued (an event on the old stream, waited for on the new
+ * one), so the old stream must still exist at that point.
  * Errors: ESTATE (no trips loaded), EINVAL (n_steps < 0), EDEVICE. */
 int32_t lpsim_step(lpsim_ctx *ctx, int32_t n_steps, void *hip_stream);
 
 /* Per-edge statistics, in input edge order (host buffers, caller-owned).
+ * Travel-time estimation is the simulator's stated purpose (abstract); each
+ * traversal's time is its exit step minus the entry step t_start that
+ * Algorithm 1 records when a vehicle enters an edge.
  *   tt_sum_steps[E]  sum over completed traversals of (exit step - entry step)
  *   n_exits[E]       number of completed traversals
  *   inflow_bin[E*B]  entries by entry bin (bin = step*dt / bin_seconds)
@@ -199,7 +205,10 @@ int32_t lpsim_edge_stats(lpsim_ctx *ctx, int64_t *tt_sum_steps, int32_t *n_exits
                          int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
                          int64_t *occ_steps_bin);
 
-/* Vehicle state per trip, trip order, input edge ids (host buffers of n_trips,
+/* Vehicle positions and speeds: the output of Algorithm 1 (vehicle position
+ * P and speed v), with the current edge and lane that Section 3.1 (vehicle
+ * data) keeps per vehicle and the lane-map cell it marks.
+ * Vehicle state per trip, trip order, input edge ids (host buffers of n_trips,
  * any may be NULL): edge (-1 unless active), lane, cell = floor(x) (-1 unless
  * active), x (m from the edge start) and v (m/s) (0 unless active),
  * arrival_step (-1 until arrived), status (LPSIM_WAITING/ACTIVE/ARRIVED).

@@ -17,22 +17,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_build", "liblpsim_oracle.so")
-_lib = None
+# the same source built with OpenMP: its two per-vehicle loops run on all host
+# cores, with results identical to the single-threaded build
+_SO_OMP = os.path.join(_HERE, "_build", "liblpsim_oracle_omp.so")
+_libs = {}
 
 ST_WAIT, ST_ACTIVE, ST_DONE = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle: gcc -O2 -ffp-contract=off, no fast-math."""
+    """Compile the oracle: gcc -O2 -ffp-contract=off, no fast-math; once
+    single-threaded and once with OpenMP."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call([
-            "gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-            "-Wall", "-shared", "-fPIC", os.path.join(_HERE, "lpsim_oracle.c"),
-            "-o", tmp, "-lm",
-        ])
-        os.replace(tmp, _SO)
+    for so, extra in ((_SO, ["-Wno-unknown-pragmas"]), (_SO_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(so):
+            tmp = so + ".tmp%d" % os.getpid()
+            subprocess.check_call([
+                "gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                "-Wall", *extra, "-shared", "-fPIC", os.path.join(_HERE, "lpsim_oracle.c"),
+                "-o", tmp, "-lm",
+            ])
+            os.replace(tmp, so)
     return _SO
 
 
@@ -55,12 +60,12 @@ class OrCounters(ctypes.Structure):
         "departures", "claims_lost", "lc_attempts", "lc_accepts", "watchdog")]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_SO):
+def _load(parallel: bool = False):
+    so = _SO_OMP if parallel else _SO
+    if so not in _libs:
+        if not os.path.exists(so):
             build(force=False)
-        lib = ctypes.CDLL(_SO)
+        lib = ctypes.CDLL(so)
         vp = ctypes.c_void_p
         lib.or_create.argtypes = [ctypes.POINTER(OrParams), ctypes.POINTER(vp)]
         lib.or_destroy.argtypes = [vp]
@@ -81,8 +86,10 @@ def _load():
         lib.or_window.restype = ctypes.c_int32
         lib.or_map_bytes.argtypes = [vp]
         lib.or_map_bytes.restype = ctypes.c_int64
-        _lib = lib
-    return _lib
+        lib.or_threads.argtypes = []
+        lib.or_threads.restype = ctypes.c_int32
+        _libs[so] = lib
+    return _libs[so]
 
 
 DEFAULTS = dict(dt=0.5, a=1.0, b=1.5, s0=2.0, T=1.5, veh_len=5.0, x0=100.0,
@@ -100,10 +107,13 @@ class OracleError(RuntimeError):
 
 
 class OracleSim:
-    """One simulation instance on the CPU oracle."""
+    """One simulation instance on the CPU oracle.  parallel=True runs the
+    OpenMP build (all host cores, OMP_NUM_THREADS if set); its results are
+    identical to the single-threaded build's."""
 
-    def __init__(self, **params):
-        lib = _load()
+    def __init__(self, parallel=False, **params):
+        self.parallel = bool(parallel)
+        self._lib = lib = _load(self.parallel)
         kw = dict(DEFAULTS)
         kw.update(params)
         self.params = kw
@@ -120,7 +130,7 @@ class OracleSim:
 
     def close(self):
         if getattr(self, "_h", None):
-            _load().or_destroy(self._h)
+            self._lib.or_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -135,7 +145,7 @@ class OracleSim:
         length = np.ascontiguousarray(length, np.float32)
         lanes = np.ascontiguousarray(lanes, np.uint8)
         speed = np.ascontiguousarray(speed, np.float32)
-        self._check(_load().or_load_network(self._h, n_nodes, len(src), _ptr(src), _ptr(dst),
+        self._check(self._lib.or_load_network(self._h, n_nodes, len(src), _ptr(src), _ptr(dst),
                                             _ptr(length), _ptr(lanes), _ptr(speed)), "load_network")
         self.n_edges = len(src)
 
@@ -145,7 +155,7 @@ class OracleSim:
         r = np.ascontiguousarray(route_edges, np.int32)
         if len(r) == 0:
             r = np.zeros(1, np.int32)
-        self._check(_load().or_load_trips(self._h, len(d), _ptr(d), _ptr(o), _ptr(r)), "load_trips")
+        self._check(self._lib.or_load_trips(self._h, len(d), _ptr(d), _ptr(o), _ptr(r)), "load_trips")
         self.n_trips = len(d)
 
     def load(self, inst):
@@ -154,36 +164,41 @@ class OracleSim:
         return self
 
     def block_edge(self, e, on=True):
-        self._check(_load().or_block_edge(self._h, e, 1 if on else 0), "block_edge")
+        self._check(self._lib.or_block_edge(self._h, e, 1 if on else 0), "block_edge")
 
     def set_signals(self, plan):
         """Fixed-time signal plan (`synth.SignalPlan`), or None to remove it."""
         if plan is None:
-            self._check(_load().or_set_signals(self._h, None, None, None, None, None), "set_signals")
+            self._check(self._lib.or_set_signals(self._h, None, None, None, None, None), "set_signals")
             return
         arrs = [np.ascontiguousarray(getattr(plan, k), np.int32)
                 for k in ("n_phases", "green", "allred", "offset", "edge_phase")]
-        self._check(_load().or_set_signals(self._h, *[_ptr(a) for a in arrs]), "set_signals")
+        self._check(self._lib.or_set_signals(self._h, *[_ptr(a) for a in arrs]), "set_signals")
 
     def place(self, trip, rp, lane, x, v):
         """Test hook: put waiting `trip` on its route edge `rp` at (lane, x, v)."""
-        self._check(_load().or_place(self._h, trip, rp, lane, float(np.float32(x)),
+        self._check(self._lib.or_place(self._h, trip, rp, lane, float(np.float32(x)),
                                      float(np.float32(v))), "place")
 
+    @property
+    def threads(self):
+        """Threads the per-vehicle loops run on (1 for the single-threaded build)."""
+        return int(self._lib.or_threads())
+
     def step(self, n=1):
-        self._check(_load().or_step(self._h, n), "step")
+        self._check(self._lib.or_step(self._h, n), "step")
 
     @property
     def W(self):
-        return _load().or_window(self._h, 0)
+        return self._lib.or_window(self._h, 0)
 
     @property
     def D(self):
-        return _load().or_window(self._h, 1)
+        return self._lib.or_window(self._h, 1)
 
     @property
     def bin_steps(self):
-        return _load().or_window(self._h, 2)
+        return self._lib.or_window(self._h, 2)
 
     def vehicles(self):
         n = self.n_trips
@@ -191,7 +206,7 @@ class OracleSim:
                    cell=np.empty(n, np.int32), x=np.empty(n, np.float32),
                    v=np.empty(n, np.float32), arrival_step=np.empty(n, np.int32),
                    status=np.empty(n, np.uint8))
-        self._check(_load().or_get_vehicles(self._h, *[_ptr(out[k]) for k in (
+        self._check(self._lib.or_get_vehicles(self._h, *[_ptr(out[k]) for k in (
             "edge", "lane", "cell", "x", "v", "arrival_step", "status")]), "get_vehicles")
         return out
 
@@ -199,7 +214,7 @@ class OracleSim:
         n = self.n_trips
         rp = np.empty(n, np.int32)
         en = np.empty(n, np.int32)
-        self._check(_load().or_get_progress(self._h, _ptr(rp), _ptr(en)), "get_progress")
+        self._check(self._lib.or_get_progress(self._h, _ptr(rp), _ptr(en)), "get_progress")
         return rp, en
 
     def edge_stats(self):
@@ -207,15 +222,15 @@ class OracleSim:
         out = dict(tt_sum=np.empty(E, np.int64), n_exits=np.empty(E, np.int32),
                    inflow_bin=np.empty((E, B), np.int32), exits_bin=np.empty((E, B), np.int32),
                    tt_bin=np.empty((E, B), np.int64), occ_bin=np.empty((E, B), np.int64))
-        self._check(_load().or_edge_stats(self._h, *[_ptr(out[k]) for k in (
+        self._check(self._lib.or_edge_stats(self._h, *[_ptr(out[k]) for k in (
             "tt_sum", "n_exits", "inflow_bin", "exits_bin", "tt_bin", "occ_bin")]), "edge_stats")
         return out
 
     def counters(self):
         c = OrCounters()
-        self._check(_load().or_get_counters(self._h, ctypes.byref(c)), "counters")
+        self._check(self._lib.or_get_counters(self._h, ctypes.byref(c)), "counters")
         return {n: int(getattr(c, n)) for n, _ in OrCounters._fields_}
 
     @property
     def invariant_broken(self):
-        return bool(_load().or_invariant_broken(self._h))
+        return bool(self._lib.or_invariant_broken(self._h))

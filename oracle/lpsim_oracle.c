@@ -59,11 +59,23 @@
  * All floating point is binary32, one rounding per operation, no contraction
  * (compile with -ffp-contract=off), evaluated in the written order.  Integer
  * and byte results are exact.
+ *
+ * Built twice from this one file: single-threaded (the parity reference), and
+ * with OpenMP over all host cores.  Only per-vehicle loops run in parallel:
+ * the longitudinal intent, the departure candidates' entry checks and the
+ * lane change each write nothing but the vehicle's own result slots; a
+ * vehicle that stays on its edge writes only its own new position and lane;
+ * painting or erasing the map writes only the vehicle's own cell.  Claims and
+ * statistics, which several vehicles touch, stay in serial loops in vehicle
+ * order, so both builds give identical results.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -550,27 +562,34 @@ static void add_entry(or_sim *s, int32_t e, int32_t step) {
     s->inflow_bin[(int64_t)e * s->p.n_bins + bin_of(s, step)] += 1;
 }
 
-/* write every active vehicle into the (all-free) map; count double occupancy */
+/* write every active vehicle into the (all-free) map; flag double occupancy.
+   A cell is taken by an exchange that returns its previous byte, so a second
+   vehicle on one cell is seen whichever vehicle is painted first (also when
+   the all-cores build paints on several threads). */
 static void paint_map(or_sim *s) {
+    int broken = 0;
+    #pragma omp parallel for schedule(static) reduction(| : broken)
     for (int64_t j = 0; j < s->n_act; j++) {
         int64_t i = s->act[j];
         int32_t c = (int32_t)floorf(s->x[i]);
         if (c < 0 || c >= s->cells[s->edge[i]] || s->lane[i] < 0 || s->lane[i] >= s->lanes[s->edge[i]]) {
-            s->invariant_broken = 1;
+            broken = 1;
             continue;
         }
         int64_t at = cell_index(s, s->edge[i], s->lane[i], c);
-        if (s->map[at] != FREE_BYTE) s->invariant_broken = 1;
-        s->map[at] = speed_byte(s->v[i]);
+        uint8_t before = __atomic_exchange_n(&s->map[at], speed_byte(s->v[i]), __ATOMIC_RELAXED);
+        if (before != FREE_BYTE) broken = 1;
     }
+    if (broken) s->invariant_broken = 1;
 }
 
 static void erase_map(or_sim *s) {
+    #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < s->n_act; j++) {
         int64_t i = s->act[j];
         int32_t c = (int32_t)floorf(s->x[i]);
         if (c < 0 || c >= s->cells[s->edge[i]] || s->lane[i] < 0 || s->lane[i] >= s->lanes[s->edge[i]]) continue;
-        s->map[cell_index(s, s->edge[i], s->lane[i], c)] = FREE_BYTE;
+        __atomic_store_n(&s->map[cell_index(s, s->edge[i], s->lane[i], c)], (uint8_t)FREE_BYTE, __ATOMIC_RELAXED);
     }
 }
 
@@ -592,7 +611,11 @@ static int step_once(or_sim *s) {
     /* map of step k */
     paint_map(s);
 
-    /* --- longitudinal intent of every active vehicle (reads step k only) --- */
+    /* --- longitudinal intent of every active vehicle (reads step k only) ---
+       Each vehicle writes only its own entries of xn, vn, kind, target and
+       tlane, so the loop may run on several threads (the all-cores build);
+       its claims are recorded afterwards, in vehicle order. */
+    #pragma omp parallel for schedule(dynamic, 2048)
     for (int64_t j = 0; j < n_act0; j++) {
         int64_t i = s->act[j];
         int32_t e = s->edge[i], l = s->lane[i];
@@ -646,10 +669,11 @@ static int step_once(or_sim *s) {
                 kind[j] = K_CLAIM;
                 target[j] = s->slot_off[en] + ln;
                 tlane[j] = ln;
-                claim(s, target[j], i);
             }
         }
     }
+    for (int64_t j = 0; j < n_act0; j++)
+        if (kind[j] == K_CLAIM) claim(s, target[j], s->act[j]);
 
     /* --- departures whose time has come (reads step k only) --- */
     int64_t n_cand = 0;
@@ -658,25 +682,38 @@ static int step_once(or_sim *s) {
         int64_t i = s->dep_order[s->dep_next++];
         if (s->status[i] == ST_WAIT) s->cand[n_cand++] = i; /* placed trips skip */
     }
+    /* each candidate checks its start lane on its own; claims in candidate order */
+    #pragma omp parallel for schedule(dynamic, 2048)
     for (int64_t q = 0; q < n_cand; q++) {
         int64_t i = s->cand[q];
         int32_t e0 = s->route[s->route_off[i]];
         int32_t l0 = (int32_t)(i % s->lanes[e0]);
         s->cand_slot[q] = s->slot_off[e0] + l0;
         s->cand_claims[q] = (uint8_t)entry_free(s, e0, l0);
-        if (s->cand_claims[q]) claim(s, s->cand_slot[q], i);
     }
+    for (int64_t q = 0; q < n_cand; q++)
+        if (s->cand_claims[q]) claim(s, s->cand_slot[q], s->cand[q]);
 
     /* the map of step k is no longer needed */
     erase_map(s);
+
+    /* --- vehicles that stay on their edge take their new position and speed
+       (each writes only its own state) --- */
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n_act0; j++) {
+        if (kind[j] != K_MOVE) continue;
+        int64_t i = s->act[j];
+        s->x[i] = xn[j];
+        s->v[i] = vn[j];
+    }
 
     /* --- resolve: the lowest id claiming a target lane enters it --- */
     int64_t n_new = 0;
     int64_t events = 0;
     for (int64_t j = 0; j < n_act0; j++) {
         int64_t i = s->act[j];
-        int32_t e = s->edge[i];
         if (kind[j] == K_ARRIVE) {
+            int32_t e = s->edge[i];
             add_exit(s, e, s->enter_step[i], k + 1);
             s->status[i] = ST_DONE;
             s->arrival_step[i] = k + 1;
@@ -687,6 +724,7 @@ static int step_once(or_sim *s) {
         }
         s->moved_edge[n_new] = 0;
         if (kind[j] == K_CLAIM) {
+            int32_t e = s->edge[i];
             if (s->claim_min[target[j]] == i) {
                 int32_t en = s->route[s->route_off[i] + s->rp[i] + 1];
                 add_exit(s, e, s->enter_step[i], k + 1);
@@ -707,9 +745,6 @@ static int step_once(or_sim *s) {
                 s->v[i] = 0.0f;
                 s->c.claims_lost++;
             }
-        } else {
-            s->x[i] = xn[j];
-            s->v[i] = vn[j];
         }
         s->next_act[n_new++] = i;
     }
@@ -749,6 +784,9 @@ static int step_once(or_sim *s) {
     if (p->lane_change) {
         paint_map(s);
         int32_t *new_lane = s->new_lane;
+        int64_t attempts = 0, accepts = 0;
+        /* each vehicle decides on the painted map and writes only new_lane[j] */
+        #pragma omp parallel for schedule(dynamic, 2048) reduction(+ : attempts, accepts)
         for (int64_t j = 0; j < n_new; j++) {
             int64_t i = s->act[j];
             new_lane[j] = s->lane[i];
@@ -768,7 +806,7 @@ static int step_once(or_sim *s) {
             float prob = d >= p->x0 ? 0.0f : 1.0f - d / p->x0;
             uint64_t h = mix64(p->seed ^ (((uint64_t)i << 32) | (uint64_t)(uint32_t)k));
             if (!((float)(h >> 40) < prob * 16777216.0f)) continue;
-            s->c.lc_attempts++;
+            attempts++;
             /* random gap terms: a second stream keyed by the same (trip, step);
                the top 24 bits give eps_a, the next 24 eps_b, each uniform on
                [-eps, eps) in steps of eps * 2^-23 */
@@ -802,10 +840,13 @@ static int step_once(or_sim *s) {
             }
             if (ok) {
                 new_lane[j] = lt;
-                s->c.lc_accepts++;
+                accepts++;
             }
         }
+        s->c.lc_attempts += attempts;
+        s->c.lc_accepts += accepts;
         erase_map(s);
+        #pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < n_new; j++) s->lane[s->act[j]] = new_lane[j];
     }
 
@@ -922,4 +963,13 @@ int or_get_counters(const or_sim *s, or_counters *out) {
 }
 
 int32_t or_invariant_broken(const or_sim *s) { return s ? s->invariant_broken : 1; }
+
+/* threads the per-vehicle loops run on (1 in the single-threaded build) */
+int32_t or_threads(void) {
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 int64_t or_map_bytes(const or_sim *s) { return s ? s->map_bytes : 0; }

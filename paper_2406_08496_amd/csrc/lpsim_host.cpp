@@ -29,7 +29,8 @@ struct lpsim_ctx {
     Params dp{};
     int device = 0;
     hipStream_t own = nullptr;
-    hipStream_t last = nullptr;
+    hipStream_t last = nullptr;   // stream of the last enqueued step work
+    hipEvent_t order_ev = nullptr;  // orders a call on a new stream after the last one
     std::string err;
     bool poisoned = false;
     void *(*ualloc)(size_t, void *) = nullptr;
@@ -70,7 +71,8 @@ struct lpsim_ctx {
     // graphs of graph_steps steps (+ reorder) and of one step, by the parity
     // of the step they start at
     hipGraphExec_t g_full[2] = {nullptr, nullptr}, g_one[2] = {nullptr, nullptr};
-    int direct_since_reorder = 0;
+    // steps since the last slot reorder, whichever way they were launched
+    int since_reorder = 0;
 
     // timing
     bool timing = false;
@@ -547,7 +549,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if ((rc = alloc_n(c, d.srank, cap, c->trip_allocs))) return rc;
     if ((rc = reset_run_state(c))) return rc;
     c->have_trips = true;
-    c->direct_since_reorder = 0;
+    c->since_reorder = 0;
     return LPSIM_OK;
 }
 
@@ -618,6 +620,8 @@ static int32_t timed(lpsim_ctx *c, const Dev &d, int phase, hipStream_t s,
     return LPSIM_OK;
 }
 
+static int reorder_interval(const lpsim_ctx *c) { return c->graph_steps > 0 ? c->graph_steps : 64; }
+
 static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     int32_t rc;
     const Dev d = dev_at(c, c->k & 1);
@@ -631,7 +635,7 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     }
     ++c->k;
     // the same reorder interval as the graphs (64 when kernels are launched singly)
-    if (++c->direct_since_reorder >= (c->graph_steps > 0 ? c->graph_steps : 64)) {
+    if (++c->since_reorder >= reorder_interval(c)) {
         const Dev dn = dev_at(c, c->k & 1);
         if (c->timing) {
             // several kernels: an event pair recorded around them
@@ -643,7 +647,7 @@ static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
         } else {
             launch_reorder(dn, c->blocks, c->threads, s);
         }
-        c->direct_since_reorder = 0;
+        c->since_reorder = 0;
     }
     HIPCHK(c, hipGetLastError());
     return LPSIM_OK;
@@ -732,6 +736,12 @@ int32_t lpsim_create(const lpsim_params *p, lpsim_ctx **out) {
         delete c;
         return LPSIM_EDEVICE;
     }
+    if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(c->own);
+        delete c;
+        return LPSIM_EDEVICE;
+    }
     c->ev.resize(2 * 512);
     c->ev_phase.resize(512);
     // timing events without the system-scope fence: they order work on the
@@ -754,6 +764,7 @@ void lpsim_destroy(lpsim_ctx *c) {
     release_net(c);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }
@@ -819,6 +830,11 @@ int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
     if (rc) return rc;
     if (n_steps < 0) return fail(c, LPSIM_EINVAL, "n_steps < 0");
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->own;
+    if (c->last && c->last != s) {
+        // work the previous call queued on another stream comes first
+        HIPCHK(c, hipEventRecord(c->order_ev, c->last));
+        HIPCHK(c, hipStreamWaitEvent(s, c->order_ev, 0));
+    }
     c->last = s;
     if (c->timing || c->graph_steps == 0) {
         for (int32_t t = 0; t < n_steps; ++t)
@@ -830,10 +846,18 @@ int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
             HIPCHK(c, hipGraphLaunch(c->g_full[c->k & 1], s));
             c->k += c->graph_steps;
             left -= c->graph_steps;
+            c->since_reorder = 0;  // the graph ends with a reorder
         }
         for (; left > 0; --left) {
             HIPCHK(c, hipGraphLaunch(c->g_one[c->k & 1], s));
             ++c->k;
+            // single steps count toward the same reorder interval, so calls
+            // shorter than a graph still compact the slots
+            if (++c->since_reorder >= reorder_interval(c)) {
+                launch_reorder(dev_at(c, c->k & 1), c->blocks, c->threads, s);
+                HIPCHK(c, hipGetLastError());
+                c->since_reorder = 0;
+            }
         }
     }
     if (!hip_stream) HIPCHK(c, hipStreamSynchronize(s));
@@ -1208,6 +1232,7 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
     HIPCHK(c, hipMemcpy(d.ctrl + (ct.k & 1), &ct, sizeof ct, hipMemcpyHostToDevice));
     c->k = ct.k;
+    c->since_reorder = 0;
     // the snapshot's cached edge flags follow the signal plan and blocked
     // edges of now, not of when it was taken
     launch_refresh_flags(dev_at(c, c->k & 1), c->own);

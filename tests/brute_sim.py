@@ -29,11 +29,17 @@ deterministic reading used throughout this project):
     rank of the next edge among the node's out-edges, even steps toward lane
     0 only, odd steps away from it, with a hashed Bernoulli draw and lead/lag
     gap acceptance; the critical gaps' random terms are uniform on
-    [-eps, eps) from a second hashed stream, added before the clamp at zero.
+    [-eps, eps) from a second hashed stream, added before the clamp at zero;
+  * statistics (Algorithm 1 records the entry time t_start of each edge):
+    entries in the bin of the entry step, finished traversals and their
+    times in the bin of their entry step, and occupancy counted step by step
+    (every vehicle on an edge at the start of a step, in that step's bin),
+    where a step's bin is floor(step * dt / bin_seconds), capped at the last.
 """
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -52,8 +58,19 @@ def splitmix_out(z: int) -> int:
 class BruteSim:
     def __init__(self, inst, dt=0.5, a=1.0, b=1.5, s0=2.0, T=1.5, veh_len=5.0,
                  x0=100.0, g_a=2.0, g_b=2.0, alpha_i=1.0, alpha_a=1.0, alpha_b=1.0,
-                 seed=0x5EED, free_mode=0, lane_change=1, eps_a=0.0, eps_b=0.0, **_ignored):
+                 seed=0x5EED, free_mode=0, lane_change=1, eps_a=0.0, eps_b=0.0,
+                 bin_seconds=300.0, n_bins=12, **_ignored):
         self.inst = inst
+        # statistics: a step's bin is floor(step * dt / bin_seconds) in exact
+        # rational arithmetic, the last bin taking every later step
+        self.bin_dt = Fraction(float(f32(dt)))
+        self.bin_len = Fraction(float(bin_seconds))
+        self.n_bins = int(n_bins)
+        E = inst.n_edges
+        self.st = {k: np.zeros((E, self.n_bins), np.int64)
+                   for k in ("inflow_bin", "exits_bin", "tt_bin", "occ_bin")}
+        self.tt_sum = np.zeros(E, np.int64)
+        self.n_exits = np.zeros(E, np.int64)
         self.dt, self.a, self.b, self.s0, self.T = f32(dt), f32(a), f32(b), f32(s0), f32(T)
         self.L, self.x0 = f32(veh_len), f32(x0)
         self.g_a, self.g_b = f32(g_a), f32(g_b)
@@ -111,6 +128,27 @@ class BruteSim:
                 return False
             pos -= r
         raise AssertionError("position outside the cycle")
+
+    # -- statistics ---------------------------------------------------------------
+    def _bin(self, step):
+        return min(math.floor(step * self.bin_dt / self.bin_len), self.n_bins - 1)
+
+    def _record_exit(self, e, enter, exit_step):
+        """A finished traversal: counted, with its time, in its entry step's bin."""
+        b = self._bin(enter)
+        self.st["exits_bin"][e, b] += 1
+        self.st["tt_bin"][e, b] += exit_step - enter
+        self.n_exits[e] += 1
+        self.tt_sum[e] += exit_step - enter
+
+    def _record_entry(self, e, step):
+        self.st["inflow_bin"][e, self._bin(step)] += 1
+
+    def stats(self):
+        out = {k: v.copy() for k, v in self.st.items()}
+        out["tt_sum"] = self.tt_sum.copy()
+        out["n_exits"] = self.n_exits.copy()
+        return out
 
     # -- occupancy queries without a map ---------------------------------------
     def _occ(self, e, l, cells=None):
@@ -182,6 +220,10 @@ class BruteSim:
                 occ_cache[(e, l)] = self._occ(e, l)
             return occ_cache[(e, l)]
 
+        # occupancy: every vehicle on an edge at the start of step k counts
+        # one step in that edge's bin of step k
+        for i in active0:
+            self.st["occ_bin"][self.e[i], self._bin(k)] += 1
         intents = {}
         requests = {}  # (edge, lane) -> list of ids
         for i in active0:
@@ -234,11 +276,14 @@ class BruteSim:
         for i in active0:
             kind, xn, vn, tgt = intents[i]
             if kind == "arrive":
+                self._record_exit(self.e[i], self.enter[i], k + 1)
                 self.status[i] = 2
                 self.arr[i] = k + 1
                 self.e[i] = -1
             elif kind == "claim":
                 if winners[tgt] == i:
+                    self._record_exit(self.e[i], self.enter[i], k + 1)
+                    self._record_entry(tgt[0], k + 1)
                     self.e[i], self.l[i] = tgt
                     self.x[i], self.v[i] = f32(0), vn
                     self.rp[i] += 1
@@ -258,6 +303,7 @@ class BruteSim:
                 self.x[i], self.v[i] = f32(0), f32(0)
                 self.rp[i] = 0
                 self.enter[i] = k + 1
+                self._record_entry(e0, k + 1)
                 entered.add(i)
         if self.lane_change:
             new_l = {}

@@ -31,15 +31,27 @@ def test_bench_byte_model_and_traffic_key():
     assert bench.MOVE_FIXED_BYTES == 40
     src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    t = bench.move_traffic_bytes()
-    if bench.MOVE_TRAFFIC["kernels_sha256"] == sha:
-        m = bench.MOVE_TRAFFIC
-        assert t == pytest.approx((m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024)
-    else:
-        assert t is None  # counters were taken on another kernel source
-    # and on one workload only
-    assert bench.move_traffic_bytes("large-x1.0") is None
-    assert bench.move_traffic_bytes(bench.MOVE_TRAFFIC_WORKLOAD + "+signals") is None
+    for key, m in bench.MOVE_TRAFFIC.items():
+        t = bench.move_traffic_bytes(*key)
+        if m["kernels_sha256"] == sha:
+            assert t == pytest.approx((m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024)
+        else:
+            assert t is None  # counters were taken on another kernel source
+    # only for the workload and window the counters were taken on
+    assert bench.move_traffic_bytes("large-x1.0", 0, 20) is None
+    assert bench.move_traffic_bytes("regional-225k-2.82M", 1, 20) is None
+
+
+def test_bench_step_byte_model():
+    import bench
+
+    d = {"vehicle_steps": 10, "scan_bytes": 7, "transfers": 2, "arrived": 1, "departures": 3,
+         "lc_attempts": 4, "claims_lost": 0, "lc_accepts": 0}
+    # 28 per vehicle-step, the scan counter, 16 per exit, 20 per departure,
+    # two look-ahead windows per lane-change attempt
+    assert bench.step_bytes(d, 41) == 28 * 10 + 7 + 16 * 3 + 20 * 3 + 2 * 41 * 4
+    assert bench.delta({k: 5 for k in bench.CNT_DELTA}, {k: 2 for k in bench.CNT_DELTA}) == \
+        {k: 3 for k in bench.CNT_DELTA}
 
 
 def test_bench_workload_names():

@@ -1,5 +1,6 @@
 """The oracle against an independent brute-force simulator (no lane map,
-all-pairs neighbour search) on tiny networks: full state equal at every step.
+all-pairs neighbour search) on tiny networks: full state and every binned
+statistic equal at every step.
 
 Congested settings (short edges, many trips, narrow departure windows) are
 chosen so that claims, losers, queues and lane changes all occur."""
@@ -15,7 +16,17 @@ from paper_2406_08496_amd import synth
 KEYS = ("status", "edge", "lane", "x", "v", "arrival_step")
 
 
+def compare_stats(o, b, where):
+    so, sb = o.edge_stats(), b.stats()
+    for key in sb:
+        if not np.array_equal(so[key], sb[key]):
+            bad = np.argwhere(so[key] != sb[key])[:5]
+            raise AssertionError(f"{where} stats {key} at {bad.tolist()}")
+
+
 def compare_run(inst, n_steps, **params):
+    # short statistics bins (10 s = 20 steps) so that runs span many of them
+    params = dict(dict(bin_seconds=10.0, n_bins=24), **params)
     o = oracle.OracleSim(**params).load(inst)
     b = BruteSim(inst, **dict(oracle.DEFAULTS, **params))
     for k in range(n_steps):
@@ -27,6 +38,7 @@ def compare_run(inst, n_steps, **params):
                 bad = np.nonzero(vo[key] != vb[key])[0][:5]
                 raise AssertionError(f"step {k} field {key} trips {bad}: "
                                      f"oracle {vo[key][bad]} brute {vb[key][bad]}")
+        compare_stats(o, b, f"step {k}")
     return o
 
 

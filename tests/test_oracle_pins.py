@@ -359,3 +359,118 @@ def test_random_terms_zero_change_nothing():
         assert np.array_equal(va[key], vb[key])
     # and nonzero terms do change the lane-change outcomes
     assert a.counters()["lc_accepts"] != c.counters()["lc_accepts"]
+
+
+# --- binned statistics (Algorithm 1: t_start recorded on entering an edge) -------
+
+def binned_line_run(steps):
+    """Two vehicles alone on a chain of four single-lane edges with dyadic
+    v0*dt (8, 8, 6.25 and 8 m per step), 10-step bins (5 s at dt 0.5), 6 bins.
+    Trip 0 departs at step 3, trip 1 at step 39; they never come within a
+    look-ahead of each other, so each follows its free-flow closed form:
+    it is on edge j from step s_j to s_{j+1} - 1, with s_0 = depart + 1 and
+    s_{j+1} = s_j + ceil(C_j / (v0_j dt)):
+        trip 0: s = 4, 17, 20, 84, arrival 88
+        trip 1: s = 40, 53, 56, 120, arrival 124."""
+    inst = synth.line_instance([100, 24, 400, 30], [16.0, 16.0, 12.5, 16.0], [1, 1, 1, 1],
+                               [3, 39], [[0, 1, 2, 3], [0, 1, 2, 3]])
+    o = oracle.OracleSim(bin_seconds=5.0, n_bins=6).load(inst)
+    o.step(steps)
+    return o
+
+
+def test_binned_stats_closed_form_after_arrival():
+    """Bin of a step = step // 10, the last bin taking every later step.
+    Entries count in the bin of the entry step; completed traversals and
+    their times in the bin of their ENTRY step; occupancy counts each step
+    a vehicle spends on the edge in that step's bin.  Hand-derived from the
+    closed-form entry steps in binned_line_run."""
+    o = binned_line_run(130)
+    v = o.vehicles()
+    assert list(v["arrival_step"]) == [88, 124]
+    s = o.edge_stats()
+    # trip 0 enters edges 0..3 at steps 4, 17, 20, 84 (bins 0, 1, 2, 5);
+    # trip 1 at 40, 53, 56, 120 (bins 4, 5, 5, 5)
+    assert s["inflow_bin"].tolist() == [[1, 0, 0, 0, 1, 0],
+                                        [0, 1, 0, 0, 0, 1],
+                                        [0, 0, 1, 0, 0, 1],
+                                        [0, 0, 0, 0, 0, 2]]
+    assert s["exits_bin"].tolist() == s["inflow_bin"].tolist()
+    # travel times 13, 3, 64, 4 steps, in the entry step's bin
+    assert s["tt_bin"].tolist() == [[13, 0, 0, 0, 13, 0],
+                                    [0, 3, 0, 0, 0, 3],
+                                    [0, 0, 64, 0, 0, 64],
+                                    [0, 0, 0, 0, 0, 8]]
+    # edge 0: trip 0 on steps 4..16 (6 in bin 0, 7 in bin 1), trip 1 on
+    # 40..52 (10 in bin 4, 3 in bin 5); edge 2: trip 0 on 20..83 (10, 10,
+    # 10 in bins 2-4, 34 in the last), trip 1 on 56..119 (64 in the last)
+    assert s["occ_bin"].tolist() == [[6, 7, 0, 0, 10, 3],
+                                     [0, 3, 0, 0, 0, 3],
+                                     [0, 0, 10, 10, 10, 98],
+                                     [0, 0, 0, 0, 0, 8]]
+    assert s["tt_sum"].tolist() == [26, 6, 128, 8]
+    assert s["n_exits"].tolist() == [2, 2, 2, 2]
+
+
+def test_binned_stats_closed_form_censored():
+    """At step 60 both trips are on edge 2 (entered at 20 and 56): their
+    traversals there are unfinished, so edge 2 has no exit and no travel
+    time yet, but its occupancy holds the steps spent so far (20..59 and
+    56..59)."""
+    o = binned_line_run(60)
+    s = o.edge_stats()
+    assert o.vehicles()["edge"].tolist() == [2, 2]
+    assert s["inflow_bin"].tolist() == [[1, 0, 0, 0, 1, 0],
+                                        [0, 1, 0, 0, 0, 1],
+                                        [0, 0, 1, 0, 0, 1],
+                                        [0, 0, 0, 0, 0, 0]]
+    assert s["exits_bin"].tolist() == [[1, 0, 0, 0, 1, 0],
+                                       [0, 1, 0, 0, 0, 1],
+                                       [0, 0, 0, 0, 0, 0],
+                                       [0, 0, 0, 0, 0, 0]]
+    assert s["tt_bin"].tolist() == [[13, 0, 0, 0, 13, 0],
+                                    [0, 3, 0, 0, 0, 3],
+                                    [0, 0, 0, 0, 0, 0],
+                                    [0, 0, 0, 0, 0, 0]]
+    assert s["occ_bin"].tolist() == [[6, 7, 0, 0, 10, 3],
+                                     [0, 3, 0, 0, 0, 3],
+                                     [0, 0, 10, 10, 10, 14],
+                                     [0, 0, 0, 0, 0, 0]]
+    assert s["tt_sum"].tolist() == [26, 6, 0, 0]
+    assert s["n_exits"].tolist() == [2, 2, 0, 0]
+
+
+# --- mandatory lane-change probability (Section 3.1, Lane Change equation) -------
+
+def lc_attempt_rate(d, trials, x0=100.0):
+    """Fraction of seeds for which vehicle B, held at rest d metres before the
+    end of its 200 m edge in the wrong lane (the only out-edge of the node
+    wants lane 0) with an empty target lane, changes lane in the first step.
+    With nobody to reject it, that is the probability of the attempt."""
+    inst = synth.line_instance([200, 50], [16.0, 16.0], [2, 2], [10**6] * 2, [[0, 1]] * 2)
+    moved = 0
+    for seed in range(1, trials + 1):
+        o = oracle.OracleSim(x0=x0, seed=seed * 104729).load(inst)
+        xb = 200.0 - d
+        o.place(0, 0, 1, xb, 0.0)
+        o.place(1, 0, 1, xb + 5.0, 0.0)  # leader at gap 0 keeps B where it is
+        o.step(1)
+        v = o.vehicles()
+        assert v["x"][0] == np.float32(xb) and v["edge"][0] == 0
+        moved += int(v["lane"][0] == 0)
+    return moved / trials
+
+
+def test_lane_change_probability_ramp():
+    """p = 1 - d/x0 inside x0 of the edge end, 0 beyond (x0 = 100 m): the
+    change rate over 500 seeds at d = 20, 50, 80 m fits (chi-squared with 3
+    degrees of freedom, 0.1% level), and no seed attempts at d >= x0."""
+    n = 500
+    chi2 = 0.0
+    for d in (20.0, 50.0, 80.0):
+        p = 1.0 - d / 100.0
+        rate = lc_attempt_rate(d, n)
+        chi2 += (rate * n - p * n) ** 2 / (n * p * (1 - p))
+    assert chi2 < 16.27, chi2
+    assert lc_attempt_rate(100.0, 100) == 0.0
+    assert lc_attempt_rate(150.0, 100) == 0.0
