@@ -8,11 +8,18 @@ a two-peak 3 h morning profile, dt = 0.5 s, horizon 28,800 steps.
 A "step" is one simulation time step of every vehicle (move, resolve, lane
 change, commit).  value = vehicle-steps / s over the timed steps (a
 vehicle-step is one vehicle active at the start of a step), inputs resident in
-device memory.  The roofline entry prices the dominant kernel's measured
-algorithmic bytes against the MI355X HBM peak; `cpu_baseline` times the plain
-CPU oracle on a bounded prefix of the same workload.
+device memory.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+With --steps K the timed window is K steps from the peak of load: the step at
+which the most vehicles are on the road (found by an untimed pass over the
+horizon), reached untimed and restored before each of the timed runs.
+Without --steps the whole horizon from step 0 is timed.  The roofline entry
+prices the dominant kernel's algorithmic bytes over the same window against
+the MI355X HBM peak; `cpu_baseline` times the plain CPU oracle (one core and
+all cores) on a bounded prefix of the same workload, with the GPU timed on
+that same prefix beside it.
 """
 from __future__ import annotations
 
@@ -46,7 +53,12 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 # counter reads for a plain device copy of known size.  A figure is reported
 # only for the workload and window it was counted on, and only while the
 # kernel source hashes to the value it was counted with; otherwise null.
-MOVE_TRAFFIC = {}
+MOVE_TRAFFIC = {
+    # profiles/k_move_regional_peak_counters.md
+    ("regional-225k-2.82M", 19136, 20): {
+        "fetch_kib": 43359.06, "fetch_scale": 2.0, "write_kib": 24104.53, "write_scale": 1.0,
+        "kernels_sha256": "5161b11eed9ab4a33091ed24691d63b4cc3fe7214637d890c7ba81ac54bb816d"},
+}
 
 
 def move_traffic_bytes(workload, start, steps):
@@ -65,6 +77,37 @@ def move_traffic_bytes(workload, start, steps):
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def summarize_profile(path, last):
+    """Summary of a rocprofv3 CSV file of this benchmark's run: for each
+    kernel, the mean over all its dispatches and over its LAST `last`
+    dispatches, which are the roofline pass (the timed window's steps with
+    the kernels launched one by one) when the run had no perceptron or CPU
+    baseline leg.  A kernel trace (`*_kernel_trace.csv`) gives durations in
+    microseconds; a counter file (`*_counter_collection.csv`) gives each
+    counter's value per dispatch.  Prints a markdown table."""
+    import csv
+    from collections import defaultdict
+
+    rows = defaultdict(list)
+    with open(path, newline="") as f:
+        rd = csv.DictReader(f)
+        counters = "Counter_Name" in rd.fieldnames
+        for r in rd:
+            name = r["Kernel_Name"]
+            key = (name, r["Counter_Name"]) if counters else (name, "duration_us")
+            val = (float(r["Counter_Value"]) if counters
+                   else (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            rows[key].append((int(r["Dispatch_Id"]), val))
+    print(f"| kernel | quantity | dispatches | mean (all) | mean (last {last}) |")
+    print("|---|---|---|---|---|")
+    for (name, what), v in sorted(rows.items(), key=lambda kv: -sum(x for _, x in kv[1])):
+        v.sort()
+        tail = [x for _, x in v[-last:]]
+        short = name.split("(")[0]
+        print(f"| {short} | {what} | {len(v)} | {sum(x for _, x in v) / len(v):.2f} | "
+              f"{sum(tail) / len(tail):.2f} |")
 
 
 def make_workload(name):
@@ -201,7 +244,13 @@ def main():
                     help="inference batch of the perceptron leg (550k edges x 4 one-hour windows)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM traffic counters")
+    ap.add_argument("--summarize-profile", default=None, metavar="CSV",
+                    help="only summarise a rocprofv3 kernel-trace or counter CSV of a run of this "
+                         "benchmark, over all dispatches and over the last --steps of each kernel")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.steps or 20)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -298,6 +347,8 @@ def main():
         sim.step(W, stream=stream)
         torch.cuda.synchronize()
     sim.restore_state(snapP)
+    # capture the graphs of a K-step call outside the timed region
+    sim.prepare(K)
 
     runs = []
     for r in range(max(1, args.repeat)):

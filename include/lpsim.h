@@ -187,6 +187,16 @@ int32_t lpsim_batch_load(lpsim_ctx *ctx, int32_t n_scen, const int32_t *node_off
  * Errors: ESTATE (no trips loaded), EINVAL (n_steps < 0), EDEVICE. */
 int32_t lpsim_step(lpsim_ctx *ctx, int32_t n_steps, void *hip_stream);
 
+/* Capture, without running anything, the HIP graphs that a call
+ * lpsim_step(ctx, n_steps, ...) made next would launch, so that the call does
+ * not pay for the capture (a caller that times or repeats calls of one
+ * length).  Steps are captured by the graph_steps of lpsim_set_launch; the
+ * rest of a call (n_steps mod graph_steps, when above 1) runs as one shorter
+ * graph, and a few such graphs are kept (the oldest replaced first).  A
+ * no-op while kernel timing is on or with graph_steps 0.  Errors: ESTATE,
+ * EINVAL (n_steps < 0), EDEVICE. */
+int32_t lpsim_prepare_steps(lpsim_ctx *ctx, int32_t n_steps);
+
 /* Per-edge statistics, in input edge order (host buffers, caller-owned).
  * Travel-time estimation is the simulator's stated purpose (abstract); each
  * traversal's time is its exit step minus the entry step t_start that

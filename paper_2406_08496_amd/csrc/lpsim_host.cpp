@@ -71,6 +71,15 @@ struct lpsim_ctx {
     // graphs of graph_steps steps (+ reorder) and of one step, by the parity
     // of the step they start at
     hipGraphExec_t g_full[2] = {nullptr, nullptr}, g_one[2] = {nullptr, nullptr};
+    // graphs of fewer than graph_steps steps, for calls (or the ends of
+    // calls) shorter than a full graph: keyed by length, starting parity and
+    // the step after which the slot reorder falls (0: none); a few are kept,
+    // the oldest replaced first
+    struct PartGraph {
+        int n, par, reorder_after;
+        hipGraphExec_t ex;
+    };
+    std::vector<PartGraph> parts;
     // steps since the last slot reorder, whichever way they were launched
     int since_reorder = 0;
 
@@ -137,6 +146,8 @@ static void drop_graphs(lpsim_ctx *c) {
         if (c->g_one[p]) (void)hipGraphExecDestroy(c->g_one[p]);
         c->g_full[p] = c->g_one[p] = nullptr;
     }
+    for (auto &g : c->parts) (void)hipGraphExecDestroy(g.ex);
+    c->parts.clear();
 }
 
 // the device view for a step of parity `par`: its control block is buffer
@@ -584,6 +595,38 @@ static int32_t build_graphs(lpsim_ctx *c) {
     return LPSIM_OK;
 }
 
+static constexpr size_t MAX_PART_GRAPHS = 8;
+
+// the graph of `n` (< graph_steps) steps from the current step, with the
+// slot reorder after step `reorder_after` of them (0: none); captured on
+// first use
+static int32_t part_graph(lpsim_ctx *c, int n, int reorder_after, hipGraphExec_t *out) {
+    const int par = c->k & 1;
+    for (auto &g : c->parts)
+        if (g.n == n && g.par == par && g.reorder_after == reorder_after) {
+            *out = g.ex;
+            return LPSIM_OK;
+        }
+    if (c->parts.size() >= MAX_PART_GRAPHS) {
+        (void)hipGraphExecDestroy(c->parts.front().ex);
+        c->parts.erase(c->parts.begin());
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->own, hipStreamCaptureModeThreadLocal));
+    for (int t = 0; t < n; ++t) {
+        enqueue_step(c, c->own, (par + t) & 1);
+        if (t + 1 == reorder_after) launch_reorder(dev_at(c, (par + t + 1) & 1), c->blocks, c->threads, c->own);
+    }
+    HIPCHK(c, hipStreamEndCapture(c->own, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e);
+    c->parts.push_back({n, par, reorder_after, ex});
+    *out = ex;
+    return LPSIM_OK;
+}
+
 static int32_t harvest_events(lpsim_ctx *c) {
     for (int i = 0; i < c->ev_used; ++i) {
         HIPCHK(c, hipEventSynchronize(c->ev[2 * i + 1]));
@@ -621,6 +664,13 @@ static int32_t timed(lpsim_ctx *c, const Dev &d, int phase, hipStream_t s,
 }
 
 static int reorder_interval(const lpsim_ctx *c) { return c->graph_steps > 0 ? c->graph_steps : 64; }
+
+// the step (1-based) of a run of n steps after which the slot reorder falls,
+// or 0 if the reorder interval does not end within them
+static int reorder_point(const lpsim_ctx *c, int n) {
+    const int r = reorder_interval(c) - c->since_reorder;
+    return (r >= 1 && r <= n) ? r : 0;
+}
 
 static int32_t step_direct(lpsim_ctx *c, hipStream_t s) {
     int32_t rc;
@@ -848,11 +898,19 @@ int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
             left -= c->graph_steps;
             c->since_reorder = 0;  // the graph ends with a reorder
         }
-        for (; left > 0; --left) {
+        if (left > 1) {
+            // the rest in one shorter graph; its steps count toward the same
+            // reorder interval, so calls shorter than a graph still compact
+            // the slots
+            const int r = reorder_point(c, left);
+            hipGraphExec_t ex = nullptr;
+            if ((rc = part_graph(c, left, r, &ex))) return rc;
+            HIPCHK(c, hipGraphLaunch(ex, s));
+            c->k += left;
+            c->since_reorder = r ? left - r : c->since_reorder + left;
+        } else if (left == 1) {
             HIPCHK(c, hipGraphLaunch(c->g_one[c->k & 1], s));
             ++c->k;
-            // single steps count toward the same reorder interval, so calls
-            // shorter than a graph still compact the slots
             if (++c->since_reorder >= reorder_interval(c)) {
                 launch_reorder(dev_at(c, c->k & 1), c->blocks, c->threads, s);
                 HIPCHK(c, hipGetLastError());
@@ -861,6 +919,28 @@ int32_t lpsim_step(lpsim_ctx *c, int32_t n_steps, void *hip_stream) {
         }
     }
     if (!hip_stream) HIPCHK(c, hipStreamSynchronize(s));
+    return LPSIM_OK;
+}
+
+int32_t lpsim_prepare_steps(lpsim_ctx *c, int32_t n_steps) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(c, LPSIM_EINVAL, "n_steps < 0");
+    if (c->timing || c->graph_steps == 0) return LPSIM_OK;
+    if (!c->g_full[0] && (rc = build_graphs(c))) return rc;
+    // the same walk as lpsim_step, without launching
+    const int left = n_steps % c->graph_steps;
+    if (left > 1) {
+        const int k0 = c->k, s0 = c->since_reorder;
+        const int full = n_steps / c->graph_steps;
+        c->k += full * c->graph_steps;
+        if (full) c->since_reorder = 0;
+        hipGraphExec_t ex = nullptr;
+        rc = part_graph(c, left, reorder_point(c, left), &ex);
+        c->k = k0;
+        c->since_reorder = s0;
+        if (rc) return rc;
+    }
     return LPSIM_OK;
 }
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "lpsim_load_trips": ([_vp, _i64, _vp, _vp, _vp], _i32),
     "lpsim_batch_load": ([_vp, _i32] + [_vp] * 13, _i32),
     "lpsim_step": ([_vp, _i32, _vp], _i32),
+    "lpsim_prepare_steps": ([_vp, _i32], _i32),
     "lpsim_edge_stats": ([_vp] + [_vp] * 6, _i32),
     "lpsim_get_vehicles": ([_vp] + [_vp] * 7, _i32),
     "lpsim_get_counters": ([_vp, ctypes.POINTER(Counters)], _i32),
@@ -231,6 +232,10 @@ class Simulator:
 
     def step(self, n=1, stream=None):
         self._check(load_library().lpsim_step(self._h, int(n), _stream_handle(stream)))
+
+    def prepare(self, n):
+        """Capture the graphs a step(n) call made next would launch."""
+        self._check(load_library().lpsim_prepare_steps(self._h, int(n)))
 
     def autotune(self, n_steps=64, block_sizes=(256, 512),
                  block_counts=(512, 640, 768, 1024, 1280, 1536, 2048)):

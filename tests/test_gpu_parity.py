@@ -150,6 +150,28 @@ def test_launch_shape_invariance(Sim, launch):
     run_pair(Sim, inst, 900, 150, launch=launch)
 
 
+def test_uneven_call_lengths(Sim):
+    """Calls of every length class: single steps, shorter graphs whose slot
+    reorder falls inside them or not at all, whole graphs plus a rest, and
+    graphs captured ahead by prepare()."""
+    case("uneven step calls with partial graphs")
+    inst = synth.grid_instance(seed=23, side=5, n_trips=900, depart_window=300, len_lo=20, len_hi=120)
+    gpu = Sim()
+    gpu.set_launch(128, 64, 16)
+    gpu.load(inst)
+    ref = oracle.OracleSim().load(inst)
+    done = 0
+    for j, n in enumerate((1, 5, 13, 15, 2, 16, 37, 1, 9, 31, 3, 17, 50, 7, 7, 7, 100, 11)):
+        if j % 3 == 0:
+            gpu.prepare(n)
+        gpu.step(n)
+        ref.step(n)
+        done += n
+        assert_same_state(gpu.vehicles(), ref.vehicles(), f"step {done} (call of {n})")
+    assert_same_stats(gpu.edge_stats(), ref.edge_stats(), f"step {done}")
+    assert_same_counters(gpu.counters(), ref.counters(), f"step {done}")
+
+
 def test_edge_order_invariance(Sim):
     case("RCB edge order vs input order")
     inst = synth.regional(0.004)
