@@ -342,6 +342,21 @@ int32_t lpsim_mlp_backward(const uint16_t *x, const uint16_t *const *h, const ui
                            const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
                            float *workspace, int32_t n_split, int64_t n, void *stream);
 
+/* lpsim_mlp_backward without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same results
+ * for the same n_split, with the data-gradient buffers and the workspace
+ * taken from a static device array of the library (24.1 MiB, held by each
+ * GPU the library runs on until the process ends).  Arguments as
+ * lpsim_mlp_backward without dz_scratch and workspace.  Limits: n <= 8192
+ * rows, n_split <= 64, else LPSIM_ECAPACITY.  n = 0 writes zero gradients
+ * with kernels (no memset).  All calls on one GPU share its array, so calls
+ * that overlap on one GPU (different streams, or threads) race; calls in one
+ * stream's order do not.  Errors: EINVAL, ECAPACITY, EDEVICE. */
+int32_t lpsim_mlp_backward_noalloc(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                                   const uint16_t *const *w, float *const *dwt, float *const *db,
+                                   int32_t n_split, int64_t n, void *stream);
+
 /* Adam step (Kingma & Ba) on one binary32 matrix [rows][cols] ("wt" layout;
  * a bias is rows = 1): m, v moment buffers, t = step count from 1.  Also
  * writes the bfloat16 copies wt_bf16 ([rows][cols]) and w_bf16 ([cols][rows]),

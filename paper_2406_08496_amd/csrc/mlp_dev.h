@@ -37,6 +37,20 @@ struct MlpBwdWeightArgs {
     int64_t n;
 };
 
+// Limits of the allocation-free backward (lpsim_mlp_backward_noalloc): its
+// data-gradient buffers (2 x rows x HID bfloat16) and weight-gradient
+// partials (slices x (HID x HID + HID) binary32) live in one static device
+// array of NOALLOC_SCRATCH_BYTES (24.1 MiB) per GPU.
+constexpr int64_t NOALLOC_MAX_ROWS = 8192;
+constexpr int NOALLOC_MAX_SPLIT = 64;
+constexpr size_t NOALLOC_DZ_BYTES = 2 * (size_t)NOALLOC_MAX_ROWS * HID * sizeof(uint16_t);
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    NOALLOC_DZ_BYTES + (size_t)NOALLOC_MAX_SPLIT * ((size_t)HID * HID + HID) * sizeof(float);
+
+// device address of this GPU's static scratch array (looked up once per
+// device, with that device current)
+hipError_t noalloc_scratch(void **out);
+
 hipError_t launch_fwd(const MlpFwdArgs &a, hipStream_t s);
 hipError_t launch_bwd_data(int layer, const MlpBwdDataArgs &a, hipStream_t s);
 hipError_t launch_bwd_weight(int layer, const MlpBwdWeightArgs &a, int n_split, hipStream_t s);

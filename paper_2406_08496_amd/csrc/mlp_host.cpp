@@ -13,6 +13,33 @@ static const int OUT_OF[4] = {HID, HID, HID, OUT};
 
 static int32_t hip_status(hipError_t e) { return e == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE; }
 
+// the backward's launches, from the last layer to the first: weight-gradient
+// partials per batch slice, their reduction in slice order, then the data
+// gradient of the layer's input (ping-pong between the two halves of
+// dz_scratch)
+static int32_t run_backward(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                            const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
+                            float *workspace, int32_t n_split, int64_t n, hipStream_t s) {
+    const uint16_t *layer_in[4] = {x, h[0], h[1], h[2]};
+    uint16_t *scratch[2] = {dz_scratch, dz_scratch + (size_t)n * HID};
+    const uint16_t *dz = dz_out;
+    int which = 0;
+    for (int l = 3; l >= 0; --l) {
+        MlpBwdWeightArgs wa{dz, layer_in[l], workspace, n};
+        hipError_t e = launch_bwd_weight(l, wa, n_split, s);
+        if (e != hipSuccess) return LPSIM_EDEVICE;
+        e = launch_reduce(workspace, n_split, OUT_OF[l], IN_OF[l], dwt[l], db[l], s);
+        if (e != hipSuccess) return LPSIM_EDEVICE;
+        if (l == 0) break;
+        MlpBwdDataArgs da{dz, w[l], layer_in[l], scratch[which], n};
+        e = launch_bwd_data(l, da, s);
+        if (e != hipSuccess) return LPSIM_EDEVICE;
+        dz = scratch[which];
+        which ^= 1;
+    }
+    return LPSIM_OK;
+}
+
 extern "C" {
 
 int32_t lpsim_mlp_shape(int32_t *in_dim, int32_t *hidden, int32_t *out_dim) {
@@ -66,24 +93,24 @@ int32_t lpsim_mlp_backward(const uint16_t *x, const uint16_t *const *h, const ui
         }
         return LPSIM_OK;
     }
-    const uint16_t *layer_in[4] = {x, h[0], h[1], h[2]};
-    uint16_t *scratch[2] = {dz_scratch, dz_scratch + (size_t)n * HID};
-    const uint16_t *dz = dz_out;
-    int which = 0;
-    for (int l = 3; l >= 0; --l) {
-        MlpBwdWeightArgs wa{dz, layer_in[l], workspace, n};
-        hipError_t e = launch_bwd_weight(l, wa, n_split, s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        e = launch_reduce(workspace, n_split, OUT_OF[l], IN_OF[l], dwt[l], db[l], s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        if (l == 0) break;
-        MlpBwdDataArgs da{dz, w[l], layer_in[l], scratch[which], n};
-        e = launch_bwd_data(l, da, s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        dz = scratch[which];
-        which ^= 1;
-    }
-    return LPSIM_OK;
+    return run_backward(x, h, dz_out, w, dwt, db, dz_scratch, workspace, n_split, n, s);
+}
+
+int32_t lpsim_mlp_backward_noalloc(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                                   const uint16_t *const *w, float *const *dwt, float *const *db, int32_t n_split,
+                                   int64_t n, void *stream) {
+    if (n < 0 || n_split < 1 || !h || !w || !dwt || !db) return LPSIM_EINVAL;
+    if (n > NOALLOC_MAX_ROWS || n_split > NOALLOC_MAX_SPLIT) return LPSIM_ECAPACITY;
+    for (int l = 0; l < 4; ++l)
+        if (!w[l] || !dwt[l] || !db[l]) return LPSIM_EINVAL;
+    if (n > 0 && (!x || !h[0] || !h[1] || !h[2] || !dz_out)) return LPSIM_EINVAL;
+    void *base = nullptr;
+    if (noalloc_scratch(&base) != hipSuccess) return LPSIM_EDEVICE;
+    uint16_t *dz_scratch = static_cast<uint16_t *>(base);
+    float *workspace = reinterpret_cast<float *>(static_cast<unsigned char *>(base) + NOALLOC_DZ_BYTES);
+    // with no rows the kernels write zero partials and zero gradients (no
+    // memset nodes, so the call can be captured in a graph)
+    return run_backward(x, h, dz_out, w, dwt, db, dz_scratch, workspace, n_split, n, (hipStream_t)stream);
 }
 
 int32_t lpsim_mlp_adam(float *w, uint16_t *wt_bf16, uint16_t *w_bf16, const float *grad, float *m, float *v,

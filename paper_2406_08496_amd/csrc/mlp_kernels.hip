@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mlp_dev.h"
 
 namespace lpsim_mlp {
@@ -389,6 +391,37 @@ hipError_t launch_adam(float *w, uint16_t *wt_bf, uint16_t *w_bf, const float *g
     hipLaunchKernelGGL(k_mlp_adam, dim3(grid ? grid : 1), dim3(256), 0, s, w, wt_bf, w_bf, g, m, v, rows, cols, lr,
                        b1, b2, eps, c1, c2);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// static scratch of the allocation-free backward.  In host code the array's
+// name stands for no device address: host code only ever uses the address
+// that hipGetSymbolAddress returns for the current device.
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace lpsim_mlp

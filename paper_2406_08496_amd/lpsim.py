@@ -93,6 +93,7 @@ SIGNATURES = {
     "lpsim_mlp_loss_grad": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], _i32),
     "lpsim_mlp_workspace_bytes": ([_i32], ctypes.c_size_t),
     "lpsim_mlp_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
+    "lpsim_mlp_backward_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
     "lpsim_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, ctypes.c_float, _i32, _vp], _i32),
     "lpsim_last_error": ([_vp], ctypes.c_char_p),
