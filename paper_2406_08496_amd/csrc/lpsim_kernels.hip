@@ -59,6 +59,15 @@ __device__ __forceinline__ void block_range(uint64_t total, uint32_t lb, uint32_
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// An empty statement that takes loaded values: the loads before it are all
+// issued before the code after it runs, so a test of one loaded value cannot
+// make the compiler sink the other loads below that test (one memory round
+// trip for all of them instead of two or more in a row).
+#define ISSUED_TOGETHER6(a, b, c, d, e, f) \
+    __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e), "+v"(f))
+#define ISSUED_TOGETHER7(a, b, c, d, e, f, g) \
+    __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e), "+v"(f), "+v"(g))
+
 // wavefront-aggregated append: returns this lane's index in `list` (valid if pred)
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
     const uint64_t mask = __ballot(pred);
@@ -82,92 +91,117 @@ __device__ __forceinline__ int32_t bin_of(const Params &p, int32_t step) {
 }
 
 // ---------------------------------------------------------------------------
-// lane-map scans with aligned 16-byte loads (the map has 256 spare bytes at
-// its end and starts 256-aligned, so whole chunks are always readable)
+// lane-map scans.  A window of cells is read as 16-byte chunks from the
+// dword boundary at or below its first byte (the memory system takes 16-byte
+// loads at any dword boundary; the map starts 256-aligned and has 256 spare
+// bytes at its end, so every chunk is readable), three chunks per group: one
+// group covers any window of up to 45 cells, so the default look-ahead of 41
+// cells is one round trip.  Inside a group the chunk holding the wanted byte
+// is picked first, then the dword inside it, with selects and no branches.
+
+constexpr uint32_t FREE_WORD = 0xffffffffu;
 
 __device__ __forceinline__ uint4 ld16(const uint8_t *map, uint32_t a) {
-    return *reinterpret_cast<const uint4 *>(map + a);
+    typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+    const u32x4_a4 r = *reinterpret_cast<const u32x4_a4 *>(map + a);
+    return make_uint4(r.x, r.y, r.z, r.w);
 }
 
-// bit mask of the occupied bytes (8 bits per byte) of an 8-byte word that lie
-// inside [s, e]; `base` is the map offset of the word's first byte
-__device__ __forceinline__ uint64_t occ_bits(uint64_t w, uint32_t base, uint32_t s, uint32_t e) {
-    uint64_t t = ~w;  // nonzero byte <=> byte != 0xFF
-    if (base < s) {
-        const uint32_t d = s - base;
-        t = d >= 8 ? 0ull : (t & (~0ull << (8 * d)));
-    }
-    if (base + 7 > e) {
-        const int32_t nb = (int32_t)e - (int32_t)base + 1;
-        t = nb <= 0 ? 0ull : (t & ((1ull << (8 * nb)) - 1ull));
-    }
-    return t;
+// occupied bits of a dword: a byte is occupied unless it is 0xFF, so any set
+// bit of ~w marks an occupied byte; the lowest set bit lies in the first one
+__device__ __forceinline__ uint32_t first_byte(uint32_t t) {
+    return (uint32_t)__builtin_ctz(t | 0x80000000u) >> 3;  // t != 0
+}
+__device__ __forceinline__ uint32_t last_byte(uint32_t t) {
+    return (31u - (uint32_t)__builtin_clz(t | 1u)) >> 3;  // t != 0
 }
 
 // first occupied cell in [lo, hi] of the lane starting at map offset `lane`,
-// or -1; *val receives its byte (the occupant's shown speed)
+// or -1; *val receives its byte (the occupant's shown speed).  Finds the
+// first occupied byte at or after the window's start and compares it with
+// the window's end, which gives the same answer.
 __device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
                                              uint32_t *val = nullptr) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
-    for (uint32_t a = s & ~15u; a <= e; a += 64) {
-        const uint32_t nch = min(4u, ((e - a) >> 4) + 1u);
-        uint4 c0 = ld16(map, a), c1, c2, c3;
-        if (nch > 1) c1 = ld16(map, a + 16);
-        if (nch > 2) c2 = ld16(map, a + 32);
-        if (nch > 3) c3 = ld16(map, a + 48);
-        for (uint32_t j = 0; j < nch; ++j) {
-            const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
-            const uint32_t b = a + 16 * j;
-            const uint64_t w0 = (uint64_t)c.x | ((uint64_t)c.y << 32), w1 = (uint64_t)c.z | ((uint64_t)c.w << 32);
-            uint64_t t = occ_bits(w0, b, s, e);
-            if (t) {
-                const uint32_t k = (uint32_t)__builtin_ctzll(t) >> 3;
-                if (val) *val = (uint32_t)(w0 >> (8 * k)) & 0xffu;
-                return (int32_t)(b + k - lane);
-            }
-            t = occ_bits(w1, b + 8, s, e);
-            if (t) {
-                const uint32_t k = (uint32_t)__builtin_ctzll(t) >> 3;
-                if (val) *val = (uint32_t)(w1 >> (8 * k)) & 0xffu;
-                return (int32_t)(b + 8 + k - lane);
-            }
+    uint32_t a = s & ~3u;
+    uint32_t below = ~(FREE_WORD << (8u * (s - a)));  // bytes before s in the first dword
+    for (;;) {
+        const uint32_t span = e - a;
+        const uint4 f = make_uint4(FREE_WORD, FREE_WORD, FREE_WORD, FREE_WORD);
+        uint4 c0 = ld16(map, a);
+        const uint4 c1 = span >= 16u ? ld16(map, a + 16) : f;
+        const uint4 c2 = span >= 32u ? ld16(map, a + 32) : f;
+        c0.x |= below;  // read bytes before s as free
+        // the first chunk with an occupied byte
+        const bool h0 = (c0.x & c0.y & c0.z & c0.w) != FREE_WORD;
+        const bool h1 = (c1.x & c1.y & c1.z & c1.w) != FREE_WORD;
+        const bool h2 = (c2.x & c2.y & c2.z & c2.w) != FREE_WORD;
+        if (h0 || h1 || h2) {
+            const uint4 c = h0 ? c0 : (h1 ? c1 : c2);
+            const uint32_t cb = h0 ? 0u : (h1 ? 16u : 32u);
+            // the first dword of that chunk with an occupied byte
+            const uint32_t tx = ~c.x, ty = ~c.y, tz = ~c.z, tw = ~c.w;
+            const uint32_t w = tx ? c.x : (ty ? c.y : (tz ? c.z : c.w));
+            const uint32_t t = tx ? tx : (ty ? ty : (tz ? tz : tw));
+            const uint32_t wb = tx ? 0u : (ty ? 4u : (tz ? 8u : 12u));
+            const uint32_t k = first_byte(t);
+            const uint32_t pos = a + cb + wb + k;
+            if (pos > e) return -1;
+            if (val) *val = (w >> (8u * k)) & 0xffu;
+            return (int32_t)(pos - lane);
         }
+        if (span < 48u) return -1;
+        a += 48u;
+        below = 0u;
     }
-    return -1;
 }
 
-// highest occupied cell in [lo, hi], or -1; *val receives its byte
+// highest occupied cell in [lo, hi], or -1; *val receives its byte.  Groups
+// are laid out from the window's first dword as in first_occ and taken from
+// the last one down; bytes after the window's end are read as free.
 __device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
                                             uint32_t *val = nullptr) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
-    const uint32_t first = s & ~15u;
-    for (int64_t a = (int64_t)(e & ~15u); a >= (int64_t)first; a -= 64) {
-        const uint32_t nch = min(4u, (uint32_t)((a - (int64_t)first) >> 4) + 1u);
-        uint4 c0 = ld16(map, (uint32_t)a), c1, c2, c3;
-        if (nch > 1) c1 = ld16(map, (uint32_t)a - 16);
-        if (nch > 2) c2 = ld16(map, (uint32_t)a - 32);
-        if (nch > 3) c3 = ld16(map, (uint32_t)a - 48);
-        for (uint32_t j = 0; j < nch; ++j) {
-            const uint4 c = j == 0 ? c0 : j == 1 ? c1 : j == 2 ? c2 : c3;
-            const uint32_t b = (uint32_t)a - 16 * j;
-            const uint64_t w0 = (uint64_t)c.x | ((uint64_t)c.y << 32), w1 = (uint64_t)c.z | ((uint64_t)c.w << 32);
-            uint64_t t = occ_bits(w1, b + 8, s, e);
-            if (t) {
-                const uint32_t k = (63u - (uint32_t)__builtin_clzll(t)) >> 3;
-                if (val) *val = (uint32_t)(w1 >> (8 * k)) & 0xffu;
-                return (int32_t)(b + 8 + k - lane);
-            }
-            t = occ_bits(w0, b, s, e);
-            if (t) {
-                const uint32_t k = (63u - (uint32_t)__builtin_clzll(t)) >> 3;
-                if (val) *val = (uint32_t)(w0 >> (8 * k)) & 0xffu;
-                return (int32_t)(b + k - lane);
+    const uint32_t a0 = s & ~3u;
+    for (uint32_t a = a0 + (e - a0) / 48u * 48u;; a -= 48u) {
+        const uint32_t span = e - a;  // 0..47 for the last group, more below it
+        const uint4 f = make_uint4(FREE_WORD, FREE_WORD, FREE_WORD, FREE_WORD);
+        const uint4 c0 = ld16(map, a);
+        uint4 c1 = span >= 16u ? ld16(map, a + 16) : f;
+        uint4 c2 = span >= 32u ? ld16(map, a + 32) : f;
+        uint4 c0m = c0;
+        // bytes after e read as free: e lies in chunk span / 16, dword (span / 4) % 4
+        if (span < 48u) {
+            const uint32_t je = span >> 2;  // dword of e, 0..11
+            const uint32_t keep = FREE_WORD >> (8u * (3u - (span & 3u)));  // bytes up to e
+            uint32_t *wd[12] = {&c0m.x, &c0m.y, &c0m.z, &c0m.w, &c1.x, &c1.y, &c1.z, &c1.w,
+                                &c2.x, &c2.y, &c2.z, &c2.w};
+#pragma unroll
+            for (uint32_t j = 0; j < 12; ++j) {
+                if (j == je) *wd[j] |= ~keep;
+                else if (j > je) *wd[j] = FREE_WORD;
             }
         }
+        const bool h0 = (c0m.x & c0m.y & c0m.z & c0m.w) != FREE_WORD;
+        const bool h1 = (c1.x & c1.y & c1.z & c1.w) != FREE_WORD;
+        const bool h2 = (c2.x & c2.y & c2.z & c2.w) != FREE_WORD;
+        if (h0 || h1 || h2) {
+            const uint4 c = h2 ? c2 : (h1 ? c1 : c0m);
+            const uint32_t cb = h2 ? 32u : (h1 ? 16u : 0u);
+            const uint32_t tx = ~c.x, ty = ~c.y, tz = ~c.z, tw = ~c.w;
+            const uint32_t w = tw ? c.w : (tz ? c.z : (ty ? c.y : c.x));
+            const uint32_t t = tw ? tw : (tz ? tz : (ty ? ty : tx));
+            const uint32_t wb = tw ? 12u : (tz ? 8u : (ty ? 4u : 0u));
+            const uint32_t k = last_byte(t);
+            const uint32_t pos = a + cb + wb + k;
+            if (pos < s) return -1;
+            if (val) *val = (w >> (8u * k)) & 0xffu;
+            return (int32_t)(pos - lane);
+        }
+        if (a == a0) return -1;
     }
-    return -1;
 }
 
 __device__ __forceinline__ uint32_t lane_base(const uint4 &E, uint32_t l) {
@@ -472,10 +506,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
         uint4 rl = make_uint4(0, 0, 0, 0);
         if (it < nv) {
             // one round of independent, coalesced loads of the vehicle's state
-            const uint32_t m = S.m[i];
-            const float x = S.x[i], v = S.v[i];
-            const uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i];
-            const float v0 = S.v0[i];
+            uint32_t m = S.m[i];
+            float x = S.x[i], v = S.v[i];
+            uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i];
+            float v0 = S.v0[i];
+            ISSUED_TOGETHER7(m, x, v, lb, cd, tlb, v0);
             if (!(m & M_DEAD)) {
                 ++alive;
                 const uint32_t lane = m & M_LANE;
@@ -487,40 +522,43 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
                 uint32_t vlb = 0;
                 const int32_t cl = first_occ(d.map, lb, c + 1, top, &vlb);
                 scanned += (uint32_t)((cl >= 0 ? cl : top) - c);
+                // the obstacle ahead: the leader (at its cell, with its
+                // byte's speed), or a closed stop line (at C, speed 0); the
+                // no-overlap clamp caps the position at lim and the speed at
+                // vcap.  One car-following evaluation serves both.
+                bool follow = cl >= 0;
+                float gap = 0.0f, vl = 0.0f, lim = 0.0f, vcap = 0.0f;
+                if (follow) {
+                    vl = (float)vlb;
+                    gap = ((float)cl - x) - p.L;
+                    lim = (float)cl - p.L;
+                    vcap = vl;
+                } else if (near) {
+                    // a red signal at the stop line (edge id and signal word
+                    // read only here), or the next edge's entry window taken
+                    // (its blocked flag is cached)
+                    bool stop = false;
+                    if (cd & CD_SIGNAL) {
+                        stop = !signal_green(d.sig[S.e[i]], k);
+                        scanned += 12u;
+                    }
+                    stop = stop || (cd & CD_NEXT_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
+                    scanned += (uint32_t)p.W;
+                    if (stop) {
+                        follow = true;
+                        gap = (float)C - x;
+                        lim = (float)(C - 1);
+                    }
+                }
                 float x2, v2;
-                if (cl >= 0) {
-                    const float vl = (float)vlb;
-                    const float gap = ((float)cl - x) - p.L;
+                if (follow) {
                     idm_follow(p, x, v, v0, gap, vl, x2, v2);
-                    const float lim = (float)cl - p.L;
                     if (x2 > lim) {
                         x2 = x > lim ? x : lim;
-                        v2 = v2 < vl ? v2 : vl;
+                        v2 = v2 < vcap ? v2 : vcap;
                     }
                 } else {
-                    bool stop = false;
-                    if (near) {
-                        // a red signal at the stop line (edge id and signal
-                        // word read only here), or the next edge's entry
-                        // window taken (its blocked flag is cached)
-                        if (cd & CD_SIGNAL) {
-                            stop = !signal_green(d.sig[S.e[i]], k);
-                            scanned += 12u;
-                        }
-                        stop = stop || (cd & CD_NEXT_BLOCKED) || first_occ(d.map, tlb, 0, p.W - 1) >= 0;
-                        scanned += (uint32_t)p.W;
-                    }
-                    if (stop) {
-                        const float gap = (float)C - x;
-                        idm_follow(p, x, v, v0, gap, 0.0f, x2, v2);
-                        const float lim = (float)(C - 1);
-                        if (x2 > lim) {
-                            x2 = x > lim ? x : lim;
-                            v2 = 0.0f;
-                        }
-                    } else {
-                        free_move(p, x, v, v0, x2, v2);
-                    }
+                    free_move(p, x, v, v0, x2, v2);
                 }
                 uint32_t kind = K_MOVE;
                 if (x2 >= (float)C) {
@@ -774,10 +812,11 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
         do {
             if (it >= ncand) break;
             i = d.lcc_list[lo + it];
-            const uint32_t m = S.m[i];
-            const float x = S.x[i], v = S.v[i];
-            const uint32_t cd = S.cd[i], lb0 = S.lb[i], id = S.id[i];
-            const int32_t e = S.e[i];
+            uint32_t m = S.m[i];
+            float x = S.x[i], v = S.v[i];
+            uint32_t cd = S.cd[i], lb0 = S.lb[i], id = S.id[i];
+            int32_t e = S.e[i];
+            ISSUED_TOGETHER7(m, x, v, cd, lb0, id, e);
             if (m & (M_DEAD | M_ENTERED)) break;  // entered its edge this step
             const int32_t C = (int32_t)(cd & 0xffffu);
             const float dist = (float)C - x;
@@ -902,17 +941,18 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d, uint32_t X, uint32_t G) 
     const uint32_t nlc = d.lc_cnt[lb];
     for (uint32_t q = threadIdx.x; q < nlc; q += blockDim.x) {
         const uint32_t i = d.lc_list[lo + q];
-        const uint32_t m = S.m[i];
+        uint32_t m = S.m[i], cd = S.cd[i], lb_old = S.lb[i];
+        float x = S.x[i], v = S.v[i];
+        int32_t en = S.en[i];
+        ISSUED_TOGETHER6(m, cd, lb_old, x, v, en);
         const uint32_t lt = m & M_LANE, lold = (m >> M_OLDLANE_SHIFT) & M_LANE;
-        const uint32_t C = S.cd[i] & 0xffffu;
-        const uint32_t lb_old = S.lb[i];
+        const uint32_t C = cd & 0xffffu;
         const uint32_t lb_new = lb_old + (lt - lold) * C;  // unsigned wrap handles lt < lold
-        const uint32_t c = (uint32_t)(int32_t)S.x[i];
+        const uint32_t c = (uint32_t)(int32_t)x;
         d.map[lb_old + c] = FREE_BYTE;
-        d.map[lb_new + c] = speed_byte(S.v[i]);
+        d.map[lb_new + c] = speed_byte(v);
         S.m[i] = lt | (m & M_REQ);
         S.lb[i] = lb_new;
-        const int32_t en = S.en[i];
         if (en >= 0) {  // entry lane on the next edge follows the lane index
             const uint4 En = d.edge[en];
             const uint32_t nle = (uint32_t)E_LANES(En);
