@@ -135,6 +135,8 @@ struct Dev {
     uint4 *wq[2];
     const uint4 *orig;    // per trip: claim word, lane-map offset of the start
                           // lane, first edge, route index of the first edge
+    const uint4 *dep_rec; // per trip: route index of the first edge, route end,
+                          // second edge (NO_NEXT if none), 0
     // per-edge counting sort of the slots (locality), every few steps
     int32_t n_edges;
     uint32_t *ecnt;       // [n_edges] vehicles per edge, zero between sorts

@@ -478,6 +478,9 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     // per-trip origin: claim word, lane-map offset of the start lane, first
     // edge, route index of the first edge (start lane = scenario-local id mod lanes)
     std::vector<uint4> orig((size_t)std::max<int64_t>(N, 1));
+    // and what a departing trip's slot needs from its route: route index of
+    // the first edge, route end, second edge (NO_NEXT if none)
+    std::vector<uint4> dep_rec((size_t)std::max<int64_t>(N, 1));
     {
         std::vector<uint4> rec_h(c->n_edges);
         HIPCHK(c, hipMemcpy(rec_h.data(), c->d.edge, (size_t)c->n_edges * 16, hipMemcpyDeviceToHost));
@@ -489,6 +492,8 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
                 const uint32_t C = R.y & 0xffffu, nl = (R.y >> 16) & 0xffu;
                 const uint32_t l0 = (uint32_t)(t - in.trip_off[s]) % nl;
                 orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, r0);
+                const uint32_t rend = roff[(size_t)t + 1];
+                dep_rec[(size_t)t] = make_uint4(r0, rend, r0 + 1 < rend ? route[r0 + 1] : NO_NEXT, 0u);
             }
         }
     }
@@ -516,6 +521,9 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     const uint4 *orig_d;
     if ((rc = upload(c, *(uint4 **)&orig_d, orig.data(), orig.size(), c->trip_allocs))) return rc;
     d.orig = orig_d;
+    const uint4 *deprec_d;
+    if ((rc = upload(c, *(uint4 **)&deprec_d, dep_rec.data(), dep_rec.size(), c->trip_allocs))) return rc;
+    d.dep_rec = deprec_d;
     if ((rc = upload(c, *(uint32_t **)&tbase_d, tbase.data(), tbase.size(), c->trip_allocs))) return rc;
     d.route = route_d;
     d.route_off = roff_d;

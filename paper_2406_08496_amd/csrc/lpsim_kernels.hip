@@ -67,6 +67,10 @@ __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
     __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e), "+v"(f))
 #define ISSUED_TOGETHER7(a, b, c, d, e, f, g) \
     __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e), "+v"(f), "+v"(g))
+#define ISSUED_TOGETHER4(a, b, c, d) __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d))
+#define ISSUED_TOGETHER9(a, b, c, d, e, f, g, h, i)                                                     \
+    __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d), "+v"(e), "+v"(f), "+v"(g), "+v"(h), \
+                     "+v"(i))
 
 // wavefront-aggregated append: returns this lane's index in `list` (valid if pred)
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred) {
@@ -116,73 +120,93 @@ __device__ __forceinline__ uint32_t last_byte(uint32_t t) {
     return (31u - (uint32_t)__builtin_clz(t | 1u)) >> 3;  // t != 0
 }
 
+// one group: three chunks from map offset a (dword-aligned); chunks that
+// start after the window's last byte e are not read and stand as free
+struct Group3 {
+    uint4 c0, c1, c2;
+};
+
+__device__ __forceinline__ Group3 load_group(const uint8_t *map, uint32_t a, uint32_t e) {
+    const uint4 f = make_uint4(FREE_WORD, FREE_WORD, FREE_WORD, FREE_WORD);
+    const uint32_t span = e - a;
+    Group3 g;
+    g.c0 = ld16(map, a);
+    g.c1 = span >= 16u ? ld16(map, a + 16) : f;
+    g.c2 = span >= 32u ? ld16(map, a + 32) : f;
+    return g;
+}
+
+// first occupied byte at or after s (a <= s <= a + 3) inside a group loaded
+// from a: its offset from a, or 48 if none; *w receives its dword
+__device__ __forceinline__ uint32_t group_first(Group3 g, uint32_t a, uint32_t s, uint32_t *w) {
+    g.c0.x |= ~(FREE_WORD << (8u * (s - a)));  // bytes before s read as free
+    const bool h0 = (g.c0.x & g.c0.y & g.c0.z & g.c0.w) != FREE_WORD;
+    const bool h1 = (g.c1.x & g.c1.y & g.c1.z & g.c1.w) != FREE_WORD;
+    const bool h2 = (g.c2.x & g.c2.y & g.c2.z & g.c2.w) != FREE_WORD;
+    // the first chunk with an occupied byte, then its first such dword
+    const uint4 c = h0 ? g.c0 : (h1 ? g.c1 : g.c2);
+    const uint32_t cb = h0 ? 0u : (h1 ? 16u : 32u);
+    const uint32_t tx = ~c.x, ty = ~c.y, tz = ~c.z, tw = ~c.w;
+    *w = tx ? c.x : (ty ? c.y : (tz ? c.z : c.w));
+    const uint32_t t = tx ? tx : (ty ? ty : (tz ? tz : tw));
+    const uint32_t wb = tx ? 0u : (ty ? 4u : (tz ? 8u : 12u));
+    return (h0 || h1 || h2) ? cb + wb + first_byte(t) : 48u;
+}
+
 // first occupied cell in [lo, hi] of the lane starting at map offset `lane`,
 // or -1; *val receives its byte (the occupant's shown speed).  Finds the
 // first occupied byte at or after the window's start and compares it with
-// the window's end, which gives the same answer.
-__device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
-                                             uint32_t *val = nullptr) {
+// the window's end, which gives the same answer.  `g`, when given, is the
+// first group, already loaded from (lane + lo) & ~3.
+__device__ __forceinline__ int32_t first_occ_in(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                                uint32_t *val, const Group3 *g0) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
-    uint32_t a = s & ~3u;
-    uint32_t below = ~(FREE_WORD << (8u * (s - a)));  // bytes before s in the first dword
-    for (;;) {
-        const uint32_t span = e - a;
-        const uint4 f = make_uint4(FREE_WORD, FREE_WORD, FREE_WORD, FREE_WORD);
-        uint4 c0 = ld16(map, a);
-        const uint4 c1 = span >= 16u ? ld16(map, a + 16) : f;
-        const uint4 c2 = span >= 32u ? ld16(map, a + 32) : f;
-        c0.x |= below;  // read bytes before s as free
-        // the first chunk with an occupied byte
-        const bool h0 = (c0.x & c0.y & c0.z & c0.w) != FREE_WORD;
-        const bool h1 = (c1.x & c1.y & c1.z & c1.w) != FREE_WORD;
-        const bool h2 = (c2.x & c2.y & c2.z & c2.w) != FREE_WORD;
-        if (h0 || h1 || h2) {
-            const uint4 c = h0 ? c0 : (h1 ? c1 : c2);
-            const uint32_t cb = h0 ? 0u : (h1 ? 16u : 32u);
-            // the first dword of that chunk with an occupied byte
-            const uint32_t tx = ~c.x, ty = ~c.y, tz = ~c.z, tw = ~c.w;
-            const uint32_t w = tx ? c.x : (ty ? c.y : (tz ? c.z : c.w));
-            const uint32_t t = tx ? tx : (ty ? ty : (tz ? tz : tw));
-            const uint32_t wb = tx ? 0u : (ty ? 4u : (tz ? 8u : 12u));
-            const uint32_t k = first_byte(t);
-            const uint32_t pos = a + cb + wb + k;
+    uint32_t a = s & ~3u, from = s;
+    for (bool first = true;; first = false) {
+        const Group3 g = (first && g0) ? *g0 : load_group(map, a, e);
+        uint32_t w;
+        const uint32_t off = group_first(g, a, from, &w);
+        if (off < 48u) {
+            const uint32_t pos = a + off;
             if (pos > e) return -1;
-            if (val) *val = (w >> (8u * k)) & 0xffu;
+            if (val) *val = (w >> (8u * (pos & 3u))) & 0xffu;
             return (int32_t)(pos - lane);
         }
-        if (span < 48u) return -1;
+        if (e - a < 48u) return -1;
         a += 48u;
-        below = 0u;
+        from = a;
     }
+}
+
+__device__ __forceinline__ int32_t first_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                             uint32_t *val = nullptr) {
+    return first_occ_in(map, lane, lo, hi, val, nullptr);
 }
 
 // highest occupied cell in [lo, hi], or -1; *val receives its byte.  Groups
 // are laid out from the window's first dword as in first_occ and taken from
 // the last one down; bytes after the window's end are read as free.
-__device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
-                                            uint32_t *val = nullptr) {
+// `g0`, when given, is the group at (lane + lo) & ~3, already loaded.
+__device__ __forceinline__ int32_t last_occ_in(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                               uint32_t *val, const Group3 *g0) {
     if (lo > hi) return -1;
     const uint32_t s = lane + (uint32_t)lo, e = lane + (uint32_t)hi;
     const uint32_t a0 = s & ~3u;
     for (uint32_t a = a0 + (e - a0) / 48u * 48u;; a -= 48u) {
         const uint32_t span = e - a;  // 0..47 for the last group, more below it
-        const uint4 f = make_uint4(FREE_WORD, FREE_WORD, FREE_WORD, FREE_WORD);
-        const uint4 c0 = ld16(map, a);
-        uint4 c1 = span >= 16u ? ld16(map, a + 16) : f;
-        uint4 c2 = span >= 32u ? ld16(map, a + 32) : f;
-        uint4 c0m = c0;
+        const Group3 g = (g0 && a == a0) ? *g0 : load_group(map, a, e);
+        uint4 c0m = g.c0, c1 = g.c1, c2 = g.c2;
         // bytes after e read as free: e lies in chunk span / 16, dword (span / 4) % 4
         if (span < 48u) {
             const uint32_t je = span >> 2;  // dword of e, 0..11
             const uint32_t keep = FREE_WORD >> (8u * (3u - (span & 3u)));  // bytes up to e
-            uint32_t *wd[12] = {&c0m.x, &c0m.y, &c0m.z, &c0m.w, &c1.x, &c1.y, &c1.z, &c1.w,
-                                &c2.x, &c2.y, &c2.z, &c2.w};
-#pragma unroll
-            for (uint32_t j = 0; j < 12; ++j) {
-                if (j == je) *wd[j] |= ~keep;
-                else if (j > je) *wd[j] = FREE_WORD;
-            }
+            auto cut = [je, keep](uint32_t w, uint32_t j) {
+                return j < je ? w : (j == je ? (w | ~keep) : FREE_WORD);
+            };
+            c0m = make_uint4(cut(c0m.x, 0), cut(c0m.y, 1), cut(c0m.z, 2), cut(c0m.w, 3));
+            c1 = make_uint4(cut(c1.x, 4), cut(c1.y, 5), cut(c1.z, 6), cut(c1.w, 7));
+            c2 = make_uint4(cut(c2.x, 8), cut(c2.y, 9), cut(c2.z, 10), cut(c2.w, 11));
         }
         const bool h0 = (c0m.x & c0m.y & c0m.z & c0m.w) != FREE_WORD;
         const bool h1 = (c1.x & c1.y & c1.z & c1.w) != FREE_WORD;
@@ -202,6 +226,11 @@ __device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, i
         }
         if (a == a0) return -1;
     }
+}
+
+__device__ __forceinline__ int32_t last_occ(const uint8_t *map, uint32_t lane, int32_t lo, int32_t hi,
+                                            uint32_t *val = nullptr) {
+    return last_occ_in(map, lane, lo, hi, val, nullptr);
 }
 
 __device__ __forceinline__ uint32_t lane_base(const uint4 &E, uint32_t l) {
@@ -360,12 +389,29 @@ __device__ __forceinline__ void share_lists(const uint32_t *cnt, uint32_t G, uin
     const uint32_t per = (G + blockDim.x - 1) / blockDim.x;
     const uint32_t b0 = threadIdx.x * per;
     uint32_t mine = 0;
-    for (uint32_t j = 0; j < per; ++j)
-        if (b0 + j < G) {
-            const uint32_t c = cnt[b0 + j];
-            s_pre[b0 + j] = c;
-            mine += c;
-        }
+    if (per <= 4) {
+        // up to four counts per thread, loaded in one round trip
+        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        if (b0 < G) c0 = cnt[b0];
+        if (per > 1 && b0 + 1 < G) c1 = cnt[b0 + 1];
+        if (per > 2 && b0 + 2 < G) c2 = cnt[b0 + 2];
+        if (per > 3 && b0 + 3 < G) c3 = cnt[b0 + 3];
+        ISSUED_TOGETHER4(c0, c1, c2, c3);
+        const uint32_t cs[4] = {c0, c1, c2, c3};
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j)
+            if (j < per && b0 + j < G) {
+                s_pre[b0 + j] = cs[j];
+                mine += cs[j];
+            }
+    } else {
+        for (uint32_t j = 0; j < per; ++j)
+            if (b0 + j < G) {
+                const uint32_t c = cnt[b0 + j];
+                s_pre[b0 + j] = c;
+                mine += c;
+            }
+    }
     uint32_t total;
     uint32_t run = block_scan(mine, wsum, total);
     for (uint32_t j = 0; j < per; ++j)
@@ -418,6 +464,33 @@ __device__ __forceinline__ bool signal_green(uint2 w, int32_t k) {
 
 __device__ __forceinline__ bool has_signal(const Dev &d, int32_t e) {
     return d.sig != nullptr && d.sig[e].x != 0u;
+}
+
+// refresh a vehicle's cached edge data from records already loaded: it is on
+// an edge with record E in `lane` (`sig`: a signal ends that edge), next edge
+// en (-1 on the last edge) with record En and aux word ax_n
+__device__ __forceinline__ void set_cache_from(const Slots &S, uint32_t i, const uint4 &E, uint32_t lane, bool sig,
+                                               int32_t en, const uint4 &En, uint32_t ax_n) {
+    S.lb[i] = lane_base(E, lane);
+    S.v0[i] = __uint_as_float(E.z);
+    uint32_t cd = (uint32_t)E_CELLS(E) | ((uint32_t)E_LOOK(E) << 16);
+    if (sig) cd |= CD_SIGNAL;
+    if (en >= 0) {
+        if (ax_n & AUX_BLOCKED) cd |= CD_NEXT_BLOCKED;
+        const uint32_t nle = (uint32_t)E_LANES(En);
+        const uint32_t ln = lane < nle - 1 ? lane : nle - 1;
+        S.tlb[i] = lane_base(En, ln);
+        S.tgt[i] = En.w + ln;
+    } else {
+        S.tlb[i] = NO_NEXT;
+        S.tgt[i] = 0;
+    }
+    S.cd[i] = cd;
+}
+
+// the lane required to leave toward an edge with aux word ax
+__device__ __forceinline__ uint32_t required_lane_of(uint32_t ax, int32_t lanes_e) {
+    return (uint32_t)(((int32_t)(ax & 0xffu) * lanes_e) / (int32_t)((ax >> 8) & 0xffu));
 }
 
 // refresh a vehicle's cached edge data: it is on edge `e` (record E) in
@@ -499,18 +572,33 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
     block_range(n, lb, G, lo64, hi64);
     const uint32_t vlo = (uint32_t)lo64, nv = (uint32_t)(hi64 - lo64);
     unsigned int alive = 0, scanned = 0;
+    // the state of this thread's next vehicle, loaded one iteration ahead
+    // (seven independent, coalesced loads), so that its round trip overlaps
+    // the lane-map reads of the current vehicle
+    uint32_t m_n = M_DEAD, lb_n = 0, cd_n = 0, tlb_n = NO_NEXT;
+    float x_n = 0.0f, v_n = 0.0f, v0_n = 0.0f;
+    auto fetch = [&](uint32_t it) {
+        if (it < nv) {
+            const uint32_t i = vlo + it;
+            m_n = S.m[i];
+            x_n = S.x[i];
+            v_n = S.v[i];
+            lb_n = S.lb[i];
+            cd_n = S.cd[i];
+            tlb_n = S.tlb[i];
+            v0_n = S.v0[i];
+        }
+    };
+    fetch(threadIdx.x);
     for (uint32_t base = 0; base < nv; base += blockDim.x) {
         const uint32_t it = base + threadIdx.x;
         const uint32_t i = vlo + it;
         bool need_resolve = false, lc_cand = false;
         uint4 rl = make_uint4(0, 0, 0, 0);
+        const uint32_t m = m_n, lb = lb_n, cd = cd_n, tlb = tlb_n;
+        const float x = x_n, v = v_n, v0 = v0_n;
+        fetch(it + blockDim.x);
         if (it < nv) {
-            // one round of independent, coalesced loads of the vehicle's state
-            uint32_t m = S.m[i];
-            float x = S.x[i], v = S.v[i];
-            uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i];
-            float v0 = S.v0[i];
-            ISSUED_TOGETHER7(m, x, v, lb, cd, tlb, v0);
             if (!(m & M_DEAD)) {
                 ++alive;
                 const uint32_t lane = m & M_LANE;
@@ -519,8 +607,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
                 // stop line inside the look-ahead: the next edge's entry matters
                 const bool near = tlb != NO_NEXT && c + D >= C;
                 const int32_t top = c + D < C - 1 ? c + D : C - 1;
+                const bool scan_own = c + 1 <= top;
+                Group3 g = {};
+                if (scan_own) g = load_group(d.map, (lb + (uint32_t)(c + 1)) & ~3u, lb + (uint32_t)top);
                 uint32_t vlb = 0;
-                const int32_t cl = first_occ(d.map, lb, c + 1, top, &vlb);
+                const int32_t cl = first_occ_in(d.map, lb, c + 1, top, &vlb, &g);
                 scanned += (uint32_t)((cl >= 0 ? cl : top) - c);
                 // the obstacle ahead: the leader (at its cell, with its
                 // byte's speed), or a closed stop line (at C, speed 0); the
@@ -629,13 +720,29 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
         const uint32_t q = pass0 + threadIdx.x;
         bool dep = false, rq = false;
         uint4 o = make_uint4(0, 0, 0, 0);
+        // a winner's edge records and route data, read before the block
+        // scans: with the claim word for candidates that made a request,
+        // then the second edge's record and aux word for winners
+        uint4 E0 = make_uint4(0, 0, 0, 0), dr = make_uint4(0, 0, NO_NEXT, 0), En0 = make_uint4(0, 0, 0, 0);
+        uint32_t ax0 = 0, sg0 = 0;
         if (q < nc) {
             bool fresh;
             o = candidate(d, ctl, q, &fresh);
-            const uint8_t claimed = d.dclaim[q];
-            if (d.claims[o.x] == o.w) {
+            uint32_t claimed = d.dclaim[q];
+            uint32_t cw = d.claims[o.x];
+            if (claimed) {
+                E0 = d.edge[o.z];
+                dr = d.dep_rec[o.w];
+                if (d.sig != nullptr) sg0 = d.sig[o.z].x;
+            }
+            ISSUED_TOGETHER4(claimed, cw, E0.x, dr.x);
+            if (cw == o.w) {
                 d.claims[o.x] = 0xffffffffu;
                 dep = true;
+                if (dr.z != NO_NEXT) {
+                    En0 = d.edge[dr.z];
+                    ax0 = d.aux[dr.z];
+                }
             } else {
                 if (claimed) atomicAdd(&cnt.c[P_LOST], 1u);
                 rq = true;
@@ -656,12 +763,9 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             const uint32_t j = o.w;
             const uint32_t ns = n + s_base[0] + my_dep;
             const int32_t e0 = (int32_t)o.z;
-            const uint32_t r0 = d.route_off[j];
-            const uint4 E0 = d.edge[e0];
             const uint32_t l0 = o.x - E0.w;
-            const uint32_t rend = d.route_off[j + 1];
-            const int32_t en0 = r0 + 1 < rend ? (int32_t)d.route[r0 + 1] : -1;
-            const uint32_t req0 = en0 >= 0 ? required_lane(d, en0, E_LANES(E0)) : 0u;
+            const int32_t en0 = dr.z != NO_NEXT ? (int32_t)dr.z : -1;
+            const uint32_t req0 = en0 >= 0 ? required_lane_of(ax0, E_LANES(E0)) : 0u;
             d.status[j] = ST_ACTIVE;
             S.x[ns] = 0.0f;
             S.v[ns] = 0.0f;
@@ -669,10 +773,10 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             S.en[ns] = en0;
             S.m[ns] = l0 | M_ENTERED | (req0 << M_REQ_SHIFT);
             S.id[ns] = j;
-            S.rp[ns] = r0;
-            S.rend[ns] = rend;
+            S.rp[ns] = dr.x;
+            S.rend[ns] = dr.y;
             S.ent[ns] = k + 1;
-            set_cache(d, S, ns, e0, E0, l0, en0);
+            set_cache_from(S, ns, E0, l0, sg0 != 0u, en0, En0, ax0);
             d.map[o.y] = speed_byte(0.0f);
             add_entry(d, e0, k + 1);
             atomicAdd(&cnt.c[P_DEPARTS], 1u);
@@ -713,7 +817,8 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
     const uint64_t chunk = share_chunk(n, G);
     for (uint32_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const uint32_t sg = seg_of(s_pre, G, q);
-        const uint4 r = d.rl_list[(uint64_t)sg * chunk + (q - s_pre[sg])];
+        uint4 r = d.rl_list[(uint64_t)sg * chunk + (q - s_pre[sg])];
+        ISSUED_TOGETHER4(r.x, r.y, r.z, r.w);
         const uint32_t kind = r.w >> 8;
         const int32_t oc = (int32_t)(r.z & 0xffffu), nc = (int32_t)(r.z >> 16);
         uint8_t *lp = d.map + r.y;
@@ -723,47 +828,56 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
             continue;
         }
         const uint32_t i = r.x;
-        const int32_t e = S.e[i];
         if (kind == K_ARRIVE) {
-            lp[oc] = FREE_BYTE;
+            const int32_t e = S.e[i], ent = S.ent[i];
             const uint32_t id = S.id[i];
+            lp[oc] = FREE_BYTE;
             d.status[id] = ST_DONE;
             d.arrival[id] = k + 1;
-            add_exit(d, e, S.ent[i], k + 1);
+            add_exit(d, e, ent, k + 1);
             S.m[i] = M_DEAD;
             atomicAdd(&cnt.c[P_ARRIVED], 1u);
             atomicAdd(&s_arr, 1u);
             s_ev = 1;
             continue;
         }
-        // entry request
-        const uint32_t tgt = d.scl[i];
-        const uint32_t id = S.id[i];
-        if (d.claims[tgt] == id) {
+        // entry request.  Round trip 1: what the slot holds for a winner or
+        // a loser; 2: the claim word, the next edge's record and the route's
+        // edge after it; 3 (winners): that edge's record and aux word
+        uint32_t tgt = d.scl[i], id = S.id[i], rp = S.rp[i], rend = S.rend[i], cdw = S.cd[i];
+        int32_t e = S.e[i], en = S.en[i], ent = S.ent[i];
+        float xo = d.sxo[i];
+        ISSUED_TOGETHER9(tgt, id, rp, rend, cdw, e, en, ent, xo);
+        uint32_t cw = d.claims[tgt];
+        uint4 En = d.edge[en];
+        int32_t en2 = rp + 2 < rend ? (int32_t)d.route[rp + 2] : -1;
+        uint32_t sig_n = d.sig != nullptr ? d.sig[en].x : 0u;
+        ISSUED_TOGETHER4(cw, En.x, en2, sig_n);
+        if (cw == id) {
+            uint4 En2 = make_uint4(0, 0, 0, 0);
+            uint32_t ax2 = 0;
+            if (en2 >= 0) {
+                En2 = d.edge[en2];
+                ax2 = d.aux[en2];
+            }
             d.claims[tgt] = 0xffffffffu;
             lp[oc] = FREE_BYTE;
-            const int32_t en = S.en[i];
-            const uint32_t rp = S.rp[i] + 1;
-            const uint32_t rend = S.rend[i];
-            const uint4 En = d.edge[en];
             const uint32_t ln = tgt - En.w;
             d.map[lane_base(En, ln)] = (uint8_t)(r.w & 0xffu);
-            add_exit(d, e, S.ent[i], k + 1);
+            add_exit(d, e, ent, k + 1);
             add_entry(d, en, k + 1);
-            const int32_t en2 = rp + 1 < rend ? (int32_t)d.route[rp + 1] : -1;
-            const uint32_t req2 = en2 >= 0 ? required_lane(d, en2, E_LANES(En)) : 0u;
+            const uint32_t req2 = en2 >= 0 ? required_lane_of(ax2, E_LANES(En)) : 0u;
             S.e[i] = en;
             S.en[i] = en2;
             S.x[i] = 0.0f;
-            S.rp[i] = rp;
+            S.rp[i] = rp + 1;
             S.ent[i] = k + 1;
             S.m[i] = ln | M_ENTERED | (req2 << M_REQ_SHIFT);
-            set_cache(d, S, i, en, En, ln, en2);
+            set_cache_from(S, i, En, ln, sig_n != 0u, en2, En2, ax2);
             atomicAdd(&cnt.c[P_TRANSFERS], 1u);
             s_ev = 1;
         } else {
-            const float xo = d.sxo[i];
-            const float lim = (float)((int32_t)(S.cd[i] & 0xffffu) - 1);
+            const float lim = (float)((int32_t)(cdw & 0xffffu) - 1);
             const float xn = xo > lim ? xo : lim;
             S.x[i] = xn;
             S.v[i] = 0.0f;
@@ -852,9 +966,17 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
             const int32_t D = (int32_t)((cd >> 16) & 0xffu);
             uint32_t vtmp = 0;
             const int32_t top = c + D < C - 1 ? c + D : C - 1;
+            const int32_t bot = c - D > 0 ? c - D : 0;
+            // the lead window's and the lag window's first groups, read
+            // together (one round trip for both scans)
+            Group3 g_lead = load_group(d.map, (lb + (uint32_t)c) & ~3u, lb + (uint32_t)top);
+            Group3 g_lag = {};
+            const bool lag_win = bot <= c - 1;
+            if (lag_win) g_lag = load_group(d.map, (lb + (uint32_t)bot) & ~3u, lb + (uint32_t)(c - 1));
+            ISSUED_TOGETHER6(g_lead.c0.x, g_lead.c1.x, g_lead.c2.x, g_lag.c0.x, g_lag.c1.x, g_lag.c2.x);
             // one scan from the target cell: occupied target cell -> no
             // change; else the first occupied cell is the lead; then the lag
-            const int32_t ca = first_occ(d.map, lb, c, top, &vtmp);
+            const int32_t ca = first_occ_in(d.map, lb, c, top, &vtmp, &g_lead);
             if (ca == c) break;
             if (ca >= 0) {
                 const float va = (float)vtmp;
@@ -863,8 +985,7 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
                 const float crit = p.g_a + (t > 0.0f ? t : 0.0f);
                 if (!(g_lead >= crit)) break;
             }
-            const int32_t bot = c - D > 0 ? c - D : 0;
-            const int32_t cb = last_occ(d.map, lb, bot, c - 1, &vtmp);
+            const int32_t cb = last_occ_in(d.map, lb, bot, c - 1, &vtmp, &g_lag);  // -1 if bot > c - 1
             if (cb >= 0) {
                 const float vb = (float)vtmp;
                 const float g_lag = (x - p.L) - (float)(cb + 1);

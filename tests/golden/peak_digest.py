@@ -45,10 +45,12 @@ def digest(vehicles, stats, counters):
     return out
 
 
-def compare(got, want, where=""):
+def compare(got, want, where="", counters=True):
     """Raise AssertionError naming the first differing counter, array and
-    chunk (chunk c covers elements [c * 2^16, (c + 1) * 2^16))."""
-    for k in COUNTER_KEYS:
+    chunk (chunk c covers elements [c * 2^16, (c + 1) * 2^16)).  counters:
+    False skips the run-wide counters (one scenario of a batch has none of
+    its own)."""
+    for k in COUNTER_KEYS if counters else ():
         if got["counters"][k] != want["counters"][k]:
             raise AssertionError(f"{where}: counter {k}: got {got['counters'][k]} want {want['counters'][k]}")
     for part in ("vehicles", "stats"):
