@@ -397,6 +397,7 @@ def main():
         "window": win,
         "trips_per_s": (c_end["arrived"] - c_start["arrived"]) / (ms / 1e3),
         "vehicle_steps": vsteps,
+        "window_counters": dw,
         "runs_ms": [round(x[0], 3) for x in runs],
     }
     if horizon_info is not None:

@@ -572,33 +572,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
     block_range(n, lb, G, lo64, hi64);
     const uint32_t vlo = (uint32_t)lo64, nv = (uint32_t)(hi64 - lo64);
     unsigned int alive = 0, scanned = 0;
-    // the state of this thread's next vehicle, loaded one iteration ahead
-    // (seven independent, coalesced loads), so that its round trip overlaps
-    // the lane-map reads of the current vehicle
-    uint32_t m_n = M_DEAD, lb_n = 0, cd_n = 0, tlb_n = NO_NEXT;
-    float x_n = 0.0f, v_n = 0.0f, v0_n = 0.0f;
-    auto fetch = [&](uint32_t it) {
-        if (it < nv) {
-            const uint32_t i = vlo + it;
-            m_n = S.m[i];
-            x_n = S.x[i];
-            v_n = S.v[i];
-            lb_n = S.lb[i];
-            cd_n = S.cd[i];
-            tlb_n = S.tlb[i];
-            v0_n = S.v0[i];
-        }
-    };
-    fetch(threadIdx.x);
     for (uint32_t base = 0; base < nv; base += blockDim.x) {
         const uint32_t it = base + threadIdx.x;
         const uint32_t i = vlo + it;
         bool need_resolve = false, lc_cand = false;
         uint4 rl = make_uint4(0, 0, 0, 0);
-        const uint32_t m = m_n, lb = lb_n, cd = cd_n, tlb = tlb_n;
-        const float x = x_n, v = v_n, v0 = v0_n;
-        fetch(it + blockDim.x);
         if (it < nv) {
+            uint32_t m = S.m[i];
+            float x = S.x[i], v = S.v[i];
+            uint32_t lb = S.lb[i], cd = S.cd[i], tlb = S.tlb[i];
+            float v0 = S.v0[i];
+            ISSUED_TOGETHER7(m, x, v, lb, cd, tlb, v0);
             if (!(m & M_DEAD)) {
                 ++alive;
                 const uint32_t lane = m & M_LANE;
