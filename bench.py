@@ -56,8 +56,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 MOVE_TRAFFIC = {
     # profiles/k_move_regional_peak_counters.md
     ("regional-225k-2.82M", 19136, 20): {
-        "fetch_kib": 43359.06, "fetch_scale": 2.0, "write_kib": 24104.53, "write_scale": 1.0,
-        "kernels_sha256": "5161b11eed9ab4a33091ed24691d63b4cc3fe7214637d890c7ba81ac54bb816d"},
+        "fetch_kib": 44321.11, "fetch_scale": 2.0, "write_kib": 24143.66, "write_scale": 1.0,
+        "kernels_sha256": "2d18b38956f2744337910bba4c72d37a9931a48c08ebe5a744b3396e8f98add0"},
 }
 
 
