@@ -36,6 +36,10 @@ constexpr uint32_t AUX_BLOCKED = 1u << 16;
 constexpr int P_VSTEPS = 0, P_TRANSFERS = 1, P_DEPARTS = 2, P_LOST = 3, P_LC_TRY = 4,
               P_LC_OK = 5, P_ARRIVED = 6, P_SCAN = 7, NPART = 8;
 constexpr int MAX_BLOCKS = 8192;
+// work-list entries beyond slot_cap: segments are rounded up to 64 entries per
+// block, and a block may read one entry per thread of its segment ahead of
+// knowing its count
+constexpr uint32_t LIST_SPARE = 64u * MAX_BLOCKS + 1024u;
 
 struct Params {
     float dt, a, b, s0, T, L, x0, g_a, g_b, al_i, al_a, al_b;
@@ -97,8 +101,10 @@ struct Dev {
     uint32_t *scl;  // claim word of a crossing vehicle (this step)
     float *sxo;     // its position before the move
     // per-step work lists, one segment per move block: move block b owns
-    // entries [lo_b, lo_b + count[b]) where [lo_b, hi_b) is its share of the
-    // slots (so no global counter is contended).  The resolve kernel deals
+    // entries [b * seg, b * seg + count[b]), where seg = list_seg(slot_cap,
+    // G) covers any block's share of the slots (so no global counter is
+    // contended, and a list's position does not depend on the step's slot
+    // count).  Lists hold slot_cap + LIST_SPARE entries.  The resolve kernel deals
     // the concatenated resolve entries out evenly (share_lists); the lane
     // change and its commit keep the move block's segment.
     uint4 *rl_list;     // vehicles with an entry request, an arrival or a changed map
@@ -107,6 +113,7 @@ struct Dev {
     uint32_t *lcc_list; // slots that may change lane
     uint32_t *lc_list;  // accepted lane changes
     uint32_t *rl_cnt, *lcc_cnt, *lc_cnt;  // [MAX_BLOCKS]
+    uint32_t slot_cap;    // slots per buffer (vehicles that can be on the road)
     uint32_t *blk_arr;  // [MAX_BLOCKS] arrivals of the block this step
     uint32_t *blk_ev;   // [MAX_BLOCKS] any entry or exit in the block this step
     const uint4 *edge;

@@ -555,9 +555,10 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     }
     if ((rc = alloc_n(c, d.scl, cap, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.sxo, cap, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.lc_list, cap, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.rl_list, cap, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.lcc_list, cap, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lc_list, cap + LIST_SPARE, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.rl_list, cap + LIST_SPARE, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.lcc_list, cap + LIST_SPARE, c->trip_allocs))) return rc;
+    d.slot_cap = (uint32_t)cap;
     if ((rc = alloc_n(c, d.rl_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.lcc_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.lc_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;

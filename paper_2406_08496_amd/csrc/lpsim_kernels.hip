@@ -443,6 +443,10 @@ __device__ __forceinline__ uint64_t share_chunk(uint64_t total, uint32_t G) {
     return (chunk + 63) & ~uint64_t(63);
 }
 
+// work-list segment per move block: a block's share of the slots at any
+// slot count (at most slot_cap) fits in it
+__device__ __forceinline__ uint64_t list_seg(const Dev &d, uint32_t G) { return share_chunk(d.slot_cap, G); }
+
 // lane required to leave toward edge `en`: the node's out-edges split the
 // lanes of the incoming edge in proportion to their rank
 __device__ __forceinline__ uint32_t required_lane(const Dev &d, int32_t en, int32_t lanes_e) {
@@ -571,6 +575,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
     uint64_t lo64, hi64;
     block_range(n, lb, G, lo64, hi64);
     const uint32_t vlo = (uint32_t)lo64, nv = (uint32_t)(hi64 - lo64);
+    const uint64_t lbase = (uint64_t)lb * list_seg(d, G);
     unsigned int alive = 0, scanned = 0;
     for (uint32_t base = 0; base < nv; base += blockDim.x) {
         const uint32_t it = base + threadIdx.x;
@@ -668,9 +673,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
             }
         }
         const uint32_t r = wave_append(&s_rl, need_resolve);
-        if (need_resolve) d.rl_list[vlo + r] = rl;
+        if (need_resolve) d.rl_list[lbase + r] = rl;
         const uint32_t q = wave_append(&s_lcc, lc_cand);
-        if (lc_cand) d.lcc_list[vlo + q] = i;
+        if (lc_cand) d.lcc_list[lbase + q] = i;
     }
     if (alive) atomicAdd(&cnt.c[P_VSTEPS], alive);
     if (scanned) atomicAdd(&cnt.c[P_SCAN], scanned);
@@ -798,10 +803,10 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
     __shared__ uint32_t wsum[32];
     uint32_t q0, q1;
     share_lists(d.rl_cnt, G, lb, s_pre, wsum, q0, q1);
-    const uint64_t chunk = share_chunk(n, G);
+    const uint64_t seg = list_seg(d, G);
     for (uint32_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
         const uint32_t sg = seg_of(s_pre, G, q);
-        uint4 r = d.rl_list[(uint64_t)sg * chunk + (q - s_pre[sg])];
+        uint4 r = d.rl_list[(uint64_t)sg * seg + (q - s_pre[sg])];
         ISSUED_TOGETHER4(r.x, r.y, r.z, r.w);
         const uint32_t kind = r.w >> 8;
         const int32_t oc = (int32_t)(r.z & 0xffffu), nc = (int32_t)(r.z >> 16);
@@ -884,11 +889,15 @@ __global__ __launch_bounds__(1024) void k_resolve(Dev d, uint32_t X) {
 __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
     __shared__ BlockCounts cnt;
     __shared__ uint32_t s_lc;
-    if (threadIdx.x == 0) s_lc = 0;
-    counts_init(&cnt);
+    // one round trip for the control block, this block's candidate count
+    // and each thread's first candidate (read ahead of the count; the list
+    // has spare entries for it)
+    const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
+    const uint64_t lo = (uint64_t)lb * list_seg(d, gridDim.x);
     Ctrl *ctl = d.ctrl;
+    const uint32_t ncand = d.lcc_cnt[lb];
+    const uint32_t i_first = d.lcc_list[lo + threadIdx.x];
     const int32_t k = ctl->k;
-    const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     const Params &p = d.p;
     // a single scenario's draw seed and trip base, read once beside the control block
@@ -899,17 +908,15 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
         seed0 = d.scen_seed[0];
         tbase0 = d.scen_tbase[0];
     }
-    uint64_t lo, hi;
-    const uint32_t lb = logical_block(blockIdx.x, gridDim.x);
-    block_range(n, lb, gridDim.x, lo, hi);
-    const uint32_t ncand = d.lcc_cnt[lb];
+    if (threadIdx.x == 0) s_lc = 0;
+    counts_init(&cnt);
     for (uint32_t base = 0; base < ncand; base += blockDim.x) {
         const uint32_t it = base + threadIdx.x;
         bool accept = false;
         uint32_t i = 0;
         do {
             if (it >= ncand) break;
-            i = d.lcc_list[lo + it];
+            i = base == 0 ? i_first : d.lcc_list[lo + it];
             uint32_t m = S.m[i];
             float x = S.x[i], v = S.v[i];
             uint32_t cd = S.cd[i], lb0 = S.lb[i], id = S.id[i];
@@ -998,21 +1005,23 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
 // writes the next step's control block
 __device__ __forceinline__ void end_part(const Dev &d, uint32_t G) {
     __shared__ uint32_t s_arr, s_ev;
-    if (threadIdx.x == 0) {
-        s_arr = 0;
-        s_ev = 0;
-    }
-    __syncthreads();
+    // the control block and the per-block flags in one round trip
+    Ctrl c{};
+    if (threadIdx.x == 0) c = *d.ctrl;
     uint32_t arr = 0, ev = 0;
     for (uint32_t b = threadIdx.x; b < G; b += blockDim.x) {
         arr += d.blk_arr[b];
         ev |= d.blk_ev[b];
     }
+    if (threadIdx.x == 0) {
+        s_arr = 0;
+        s_ev = 0;
+    }
+    __syncthreads();
     if (arr) atomicAdd(&s_arr, arr);
     if (ev) s_ev = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const Ctrl c = *d.ctrl;
         Ctrl nx = c;
         const bool any = s_ev != 0 || c.dep_ev != 0;
         nx.watchdog = (c.n_alive > 0 && !any) ? c.watchdog + 1 : 0;
@@ -1038,14 +1047,15 @@ __global__ __launch_bounds__(1024) void k_commit(Dev d, uint32_t X, uint32_t G) 
         return;
     }
     const Ctrl *ctl = d.ctrl;
-    const uint32_t n = ctl->n_slots;
-    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    uint64_t lo, hi;
     const uint32_t lb = logical_block(blockIdx.x - X, G);
-    block_range(n, lb, G, lo, hi);
+    const uint64_t lo = (uint64_t)lb * list_seg(d, G);
+    // the count and each thread's first entry in one round trip with the
+    // control block (the list has spare entries for the read ahead)
     const uint32_t nlc = d.lc_cnt[lb];
+    const uint32_t i_first = d.lc_list[lo + threadIdx.x];
+    const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     for (uint32_t q = threadIdx.x; q < nlc; q += blockDim.x) {
-        const uint32_t i = d.lc_list[lo + q];
+        const uint32_t i = q == threadIdx.x ? i_first : d.lc_list[lo + q];
         uint32_t m = S.m[i], cd = S.cd[i], lb_old = S.lb[i];
         float x = S.x[i], v = S.v[i];
         int32_t en = S.en[i];
