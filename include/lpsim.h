@@ -389,6 +389,17 @@ void lpsim_router_destroy(lpsim_router *r);
 int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
                            const int32_t *dest);
 
+/* lpsim_router_solve with the trees computed on the current GPU: the same
+ * fixed point dist[x] = min over out-edges e = (x -> y) of dist[y] + cost[e]
+ * in float64, the same lowest-edge-id rule among equally short choices, so
+ * the same routes.  Label-correcting relaxation over (destination, node)
+ * pairs with 64-bit atomic minima, then one pass that picks each node's tree
+ * edge.  `stream` is a hipStream_t or NULL; the call returns when the trees
+ * are on the host.  Device memory for the graph is kept until
+ * lpsim_router_destroy.  Errors: as lpsim_router_solve, and EDEVICE. */
+int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                               const int32_t *dest, void *stream);
+
 /* Write the routes of the last solve (host buffers).  take_new (n_trips
  * flags) NULL takes every new route; otherwise trip i keeps its old route
  * (old_off / old_edges) where take_new[i] == 0.  out_off receives n_trips+1

@@ -51,8 +51,10 @@ def msa_switch(n_trips, n, seed):
 class Router:
     """Shortest-time routes (library host code, lpsim_router_*)."""
 
-    def __init__(self, n_nodes, src, dst, n_threads=0):
+    def __init__(self, n_nodes, src, dst, n_threads=0, gpu=False):
+        """gpu: compute the trees on the GPU (same routes as the host solve)."""
         self.lib = load_library()
+        self.gpu = gpu
         self.src = np.ascontiguousarray(src, np.int32)
         self.dst = np.ascontiguousarray(dst, np.int32)
         h = ctypes.c_void_p()
@@ -72,7 +74,13 @@ class Router:
         origin = np.ascontiguousarray(origin, np.int32)
         dest = np.ascontiguousarray(dest, np.int32)
         n = len(origin)
-        rc = self.lib.lpsim_router_solve(self._h, _p(cost), n, _p(origin), _p(dest))
+        if self.gpu:
+            import torch
+
+            rc = self.lib.lpsim_router_solve_gpu(self._h, _p(cost), n, _p(origin), _p(dest),
+                                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        else:
+            rc = self.lib.lpsim_router_solve(self._h, _p(cost), n, _p(origin), _p(dest))
         if rc:
             raise LpsimError(rc, "router solve (bad cost, ids, or unreachable destination)")
         off = np.empty(n + 1, np.int64)

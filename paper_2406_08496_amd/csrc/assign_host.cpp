@@ -18,7 +18,18 @@
 #include <unordered_map>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "lpsim.h"
+
+namespace lpsim_route {
+struct GpuRouter;
+void gpu_router_free(GpuRouter *g);
+int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const int64_t *in_off_h,
+                         const int32_t *in_edges_h, const int32_t *in_src_h, const int32_t *src_h,
+                         const int32_t *dst_h, const double *cost_h, const int32_t *dests, int32_t nd,
+                         int32_t *next_edge, hipStream_t s);
+}  // namespace lpsim_route
 
 struct lpsim_router {
     int32_t n_nodes = 0, n_edges = 0, n_threads = 1;
@@ -34,6 +45,7 @@ struct lpsim_router {
     std::vector<int32_t> next_edge;  // [dest][node]
     std::vector<int32_t> len;        // per trip, new route length (trips taking one)
     bool solved = false;
+    lpsim_route::GpuRouter *gpu = nullptr;  // device copy of the graph (GPU solves)
 };
 
 namespace {
@@ -128,10 +140,16 @@ int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src
     return LPSIM_OK;
 }
 
-void lpsim_router_destroy(lpsim_router *r) { delete r; }
+void lpsim_router_destroy(lpsim_router *r) {
+    if (!r) return;
+    lpsim_route::gpu_router_free(r->gpu);
+    delete r;
+}
 
-int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
-                           const int32_t *dest) {
+// both solves: the trees toward every distinct destination, on the host
+// (std::thread workers) or on the GPU on `stream`
+static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                            const int32_t *dest, bool on_gpu, void *stream) {
     if (!r || !cost || n_trips < 0 || (n_trips > 0 && (!origin || !dest))) return LPSIM_EINVAL;
     for (int32_t e = 0; e < r->n_edges; ++e)
         if (!(cost[e] > 0.0) || !std::isfinite(cost[e])) return LPSIM_EINVAL;
@@ -154,6 +172,12 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
         }
         const int32_t nd = (int32_t)r->dests.size();
         r->next_edge.assign((size_t)nd * r->n_nodes, -1);
+        if (on_gpu) {
+            const int32_t rc = lpsim_route::gpu_router_solve(
+                &r->gpu, r->n_nodes, r->n_edges, r->in_off.data(), r->in_edges.data(), r->in_src.data(),
+                r->src.data(), r->dst.data(), cost, r->dests.data(), nd, r->next_edge.data(), (hipStream_t)stream);
+            if (rc) return rc;
+        }
         r->in_cost.resize(r->in_edges.size());
         for (size_t j = 0; j < r->in_edges.size(); ++j) r->in_cost[j] = cost[r->in_edges[j]];
         const int32_t nw = std::max(1, std::min(r->n_threads, nd));
@@ -169,10 +193,12 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
                         done[w], heap[w]);
             }
         };
-        std::vector<std::thread> pool;
-        for (int32_t w = 1; w < nw; ++w) pool.emplace_back(worker, w);
-        worker(0);
-        for (auto &t : pool) t.join();
+        if (!on_gpu) {
+            std::vector<std::thread> pool;
+            for (int32_t w = 1; w < nw; ++w) pool.emplace_back(worker, w);
+            worker(0);
+            for (auto &t : pool) t.join();
+        }
         // every destination reachable: the origin has an edge toward it (a
         // shortest-path tree then leads there); route lengths are measured
         // by lpsim_router_fill for the trips that take a new route
@@ -185,6 +211,16 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
     }
     r->solved = true;
     return LPSIM_OK;
+}
+
+int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                           const int32_t *dest) {
+    return router_solve(r, cost, n_trips, origin, dest, false, nullptr);
+}
+
+int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
+                               const int32_t *dest, void *stream) {
+    return router_solve(r, cost, n_trips, origin, dest, true, stream);
 }
 
 int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t *old_edges, const uint8_t *take_new,

@@ -61,12 +61,27 @@ __device__ __forceinline__ void hidden_layer(const uint16_t *A, int lda, const u
     f32x4 acc[RB][CB];
     for (int rb = 0; rb < RB; ++rb)
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // weight fragments come from L2; the next k-step's are loaded while the
+    // current step's products run
+    bf16x8 b[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) b[cb] = frag(wt + (size_t)((w * CB + cb) * 16 + r16) * K + kq);
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 b[CB];
-        for (int cb = 0; cb < CB; ++cb) b[cb] = frag(wt + (size_t)((w * CB + cb) * 16 + r16) * K + k0 + kq);
+        bf16x8 bn[CB];
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) bn[cb] = frag(wt + (size_t)((w * CB + cb) * 16 + r16) * K + k0 + 32 + kq);
+        }
+#pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const bf16x8 a = frag(A + (rb * 16 + r16) * lda + k0 + kq);
+#pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a, b[cb], acc[rb][cb]);
+        }
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) b[cb] = bn[cb];
         }
     }
     for (int cb = 0; cb < CB; ++cb) {

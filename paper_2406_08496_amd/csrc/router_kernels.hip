@@ -1,0 +1,285 @@
+// router_kernels.hip -- shortest-time trees toward many destinations at once
+// on the GPU, for the traffic-assignment loop's routing step.
+//
+// For every destination t the trees solve, in float64,
+//     dist[t] = 0,   dist[x] = min over out-edges e = (x -> y) of dist[y] + cost[e],
+// the fixed point that a backward Dijkstra settles, and give each node the
+// lowest-numbered out-edge that attains the minimum (so the tree does not
+// depend on any processing order).  The distances come from label-correcting
+// relaxation over a frontier of (destination, node) pairs: a pair whose
+// distance dropped relaxes the in-edges of its node with a 64-bit atomic
+// minimum on the distance bits (non-negative doubles order like their bit
+// patterns), and every drop queues the upstream pair once.  The fixed point
+// is unique, so the order of relaxations does not change it.  The tree
+// edges are then picked in a separate pass that compares each out-edge's
+// candidate with the final distance, exactly as the Dijkstra's tie rule does.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "lpsim.h"
+
+namespace lpsim_route {
+
+constexpr unsigned long long INF_BITS = 0x7ff0000000000000ull;  // +infinity
+constexpr int THREADS = 256;
+constexpr int GRID = 2048;         // blocks of the grid-stride kernels
+constexpr int PUSH_BUF = 4 * THREADS;  // per-block staging of queued pairs
+
+struct GpuRouter {
+    int32_t n = 0, m = 0;
+    // incoming edges per node (CSR) with their upstream node; outgoing
+    // edges per node in increasing edge id with their downstream node
+    int32_t *in_off = nullptr, *in_src = nullptr, *in_edge = nullptr;
+    int32_t *out_off = nullptr, *out_dst = nullptr, *out_edge = nullptr;
+    double *in_cost = nullptr, *out_cost = nullptr, *cost = nullptr;
+    // per destination batch
+    size_t cap_pairs = 0;        // destinations x nodes the buffers hold
+    unsigned long long *dist = nullptr;
+    uint2 *front[2] = {nullptr, nullptr};
+    uint32_t *flags[2] = {nullptr, nullptr};  // one bit per pair
+    uint32_t *count = nullptr;                // [2] frontier sizes
+    int32_t *targets = nullptr;
+    int32_t *nx = nullptr;
+    std::vector<void *> allocs;
+};
+
+__global__ void k_costs(GpuRouter g) {
+    for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < g.m; j += gridDim.x * blockDim.x) {
+        g.in_cost[j] = g.cost[g.in_edge[j]];
+        g.out_cost[j] = g.cost[g.out_edge[j]];
+    }
+}
+
+// all distances infinite but each destination's own, which starts the frontier
+__global__ void k_init(GpuRouter g, int32_t nd) {
+    const size_t total = (size_t)nd * g.n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        g.dist[i] = INF_BITS;
+    const size_t words = (total + 31) / 32;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x) {
+        g.flags[0][i] = 0;
+        g.flags[1][i] = 0;
+    }
+}
+
+__global__ void k_seed(GpuRouter g, int32_t nd) {
+    for (int32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
+        const size_t pair = (size_t)d * g.n + (size_t)g.targets[d];
+        g.dist[pair] = 0ull;
+        g.front[0][d] = make_uint2((uint32_t)d, (uint32_t)g.targets[d]);
+        atomicOr(&g.flags[0][pair >> 5], 1u << (pair & 31));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        g.count[0] = (uint32_t)nd;
+        g.count[1] = 0;
+    }
+}
+
+// one round: every queued pair relaxes the in-edges of its node; pairs whose
+// distance drops are queued (once) for the next round
+__global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t cur) {
+    __shared__ uint2 buf[PUSH_BUF];
+    __shared__ uint32_t n_buf, base;
+    const uint32_t nf = g.count[cur];
+    const uint2 *front = g.front[cur];
+    uint2 *next = g.front[cur ^ 1];
+    uint32_t *nflags = g.flags[cur ^ 1];
+    uint32_t *ncount = &g.count[cur ^ 1];
+    for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < nf; t0 += gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) n_buf = 0;
+        __syncthreads();
+        const uint32_t t = t0 + threadIdx.x;
+        if (t < nf) {
+            const uint2 it = front[t];
+            const size_t row = (size_t)it.x * g.n;
+            unsigned long long *dd = g.dist + row;
+            const double dy = __longlong_as_double((long long)dd[it.y]);
+            for (int32_t j = g.in_off[it.y]; j < g.in_off[it.y + 1]; ++j) {
+                const int32_t x = g.in_src[j];
+                const unsigned long long cb = (unsigned long long)__double_as_longlong(dy + g.in_cost[j]);
+                if (cb >= dd[x]) continue;
+                const unsigned long long old = atomicMin(&dd[x], cb);
+                if (cb >= old) continue;
+                const size_t pair = row + (size_t)x;
+                const uint32_t bit = 1u << (pair & 31);
+                if (atomicOr(&nflags[pair >> 5], bit) & bit) continue;  // already queued
+                const uint32_t k = atomicAdd(&n_buf, 1u);
+                if (k < PUSH_BUF) {
+                    buf[k] = make_uint2(it.x, (uint32_t)x);
+                } else {
+                    next[atomicAdd(ncount, 1u)] = make_uint2(it.x, (uint32_t)x);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t nb = n_buf < PUSH_BUF ? n_buf : PUSH_BUF;
+        if (threadIdx.x == 0 && nb) base = atomicAdd(ncount, nb);
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) next[base + k] = buf[k];
+        __syncthreads();
+    }
+}
+
+// after a round: the processed frontier's flags are cleared and its count
+// reset, so the buffer can take the round after next
+__global__ void k_retire(GpuRouter g, int32_t cur) {
+    const uint32_t nf = g.count[cur];
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += gridDim.x * blockDim.x) {
+        const uint2 it = g.front[cur][t];
+        const size_t pair = (size_t)it.x * g.n + it.y;
+        g.flags[cur][pair >> 5] = 0u;
+    }
+}
+
+__global__ void k_reset_count(GpuRouter g, int32_t cur) { g.count[cur] = 0; }
+
+// tree edge of every (destination, node): the lowest out-edge whose
+// candidate equals the node's distance (-1 at the destination or if the
+// destination cannot be reached)
+__global__ void k_ties(GpuRouter g, int32_t nd) {
+    const size_t total = (size_t)nd * g.n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int32_t d = (int32_t)(i / g.n), x = (int32_t)(i - (size_t)d * g.n);
+        int32_t best = -1;
+        const unsigned long long dx = g.dist[i];
+        if (x != g.targets[d] && dx != INF_BITS) {
+            const unsigned long long *dd = g.dist + (size_t)d * g.n;
+            for (int32_t j = g.out_off[x]; j < g.out_off[x + 1]; ++j) {
+                const double cand = __longlong_as_double((long long)dd[g.out_dst[j]]) + g.out_cost[j];
+                if ((unsigned long long)__double_as_longlong(cand) == dx) {
+                    best = g.out_edge[j];
+                    break;
+                }
+            }
+        }
+        g.nx[i] = best;
+    }
+}
+
+static int32_t status(hipError_t e) { return e == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE; }
+
+template <class T>
+static hipError_t alloc(GpuRouter *g, T *&p, size_t n) {
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    g->allocs.push_back(q);
+    p = static_cast<T *>(q);
+    return hipSuccess;
+}
+
+void gpu_router_free(GpuRouter *g) {
+    if (!g) return;
+    for (void *p : g->allocs) (void)hipFree(p);
+    delete g;
+}
+
+#define RCHK(call)                                   \
+    do {                                             \
+        const hipError_t e_ = (call);                \
+        if (e_ != hipSuccess) return status(e_);     \
+    } while (0)
+
+// Trees toward `nd` destinations (host ids) for edge costs `cost` (host,
+// n_edges): next_edge (host, nd x n_nodes) receives each node's tree edge.
+// The graph (host CSR arrays) is uploaded on the first call.
+int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const int64_t *in_off_h,
+                         const int32_t *in_edges_h, const int32_t *in_src_h, const int32_t *src_h,
+                         const int32_t *dst_h, const double *cost_h, const int32_t *dests, int32_t nd,
+                         int32_t *next_edge, hipStream_t s) {
+    if (!*gp) {
+        GpuRouter *g = new (std::nothrow) GpuRouter();
+        if (!g) return LPSIM_ENOMEM;
+        *gp = g;
+        g->n = n_nodes;
+        g->m = n_edges;
+        std::vector<int32_t> io((size_t)n_nodes + 1), oo((size_t)n_nodes + 1, 0), od((size_t)n_edges),
+            oe((size_t)n_edges);
+        for (size_t u = 0; u <= (size_t)n_nodes; ++u) io[u] = (int32_t)in_off_h[u];
+        for (int32_t e = 0; e < n_edges; ++e) oo[(size_t)src_h[e] + 1]++;
+        for (int32_t u = 0; u < n_nodes; ++u) oo[(size_t)u + 1] += oo[(size_t)u];
+        {
+            std::vector<int32_t> pos(oo.begin(), oo.end() - 1);
+            for (int32_t e = 0; e < n_edges; ++e) {  // increasing edge id within each node
+                const int32_t k = pos[(size_t)src_h[e]]++;
+                oe[(size_t)k] = e;
+                od[(size_t)k] = dst_h[e];
+            }
+        }
+        RCHK(alloc(g, g->in_off, (size_t)n_nodes + 1));
+        RCHK(alloc(g, g->in_src, (size_t)n_edges));
+        RCHK(alloc(g, g->in_edge, (size_t)n_edges));
+        RCHK(alloc(g, g->out_off, (size_t)n_nodes + 1));
+        RCHK(alloc(g, g->out_dst, (size_t)n_edges));
+        RCHK(alloc(g, g->out_edge, (size_t)n_edges));
+        RCHK(alloc(g, g->in_cost, (size_t)n_edges));
+        RCHK(alloc(g, g->out_cost, (size_t)n_edges));
+        RCHK(alloc(g, g->cost, (size_t)n_edges));
+        RCHK(alloc(g, g->count, 2));
+        RCHK(hipMemcpy(g->in_off, io.data(), io.size() * 4, hipMemcpyHostToDevice));
+        RCHK(hipMemcpy(g->in_src, in_src_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
+        RCHK(hipMemcpy(g->in_edge, in_edges_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
+        RCHK(hipMemcpy(g->out_off, oo.data(), oo.size() * 4, hipMemcpyHostToDevice));
+        RCHK(hipMemcpy(g->out_dst, od.data(), od.size() * 4, hipMemcpyHostToDevice));
+        RCHK(hipMemcpy(g->out_edge, oe.data(), oe.size() * 4, hipMemcpyHostToDevice));
+    }
+    GpuRouter *g = *gp;
+    if (g->n != n_nodes || g->m != n_edges) return LPSIM_EINVAL;
+    // destinations per batch: distances, frontiers and flags of at most 64M pairs
+    const int32_t per = std::max<int32_t>(1, std::min<int32_t>(nd, (int32_t)((64ll << 20) / n_nodes)));
+    const size_t pairs = (size_t)per * (size_t)n_nodes;
+    if (g->cap_pairs < pairs) {
+        // grow the batch buffers (freed with the router)
+        RCHK(alloc(g, g->dist, pairs));
+        RCHK(alloc(g, g->front[0], pairs));
+        RCHK(alloc(g, g->front[1], pairs));
+        RCHK(alloc(g, g->flags[0], (pairs + 31) / 32));
+        RCHK(alloc(g, g->flags[1], (pairs + 31) / 32));
+        RCHK(alloc(g, g->nx, pairs));
+        RCHK(alloc(g, g->targets, (size_t)per));
+        g->cap_pairs = pairs;
+    }
+    RCHK(hipMemcpyAsync(g->cost, cost_h, (size_t)n_edges * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_costs, dim3(GRID), dim3(THREADS), 0, s, *g);
+    RCHK(hipGetLastError());
+    for (int32_t d0 = 0; d0 < nd; d0 += per) {
+        const int32_t nb = std::min(per, nd - d0);
+        RCHK(hipMemcpyAsync(g->targets, dests + d0, (size_t)nb * 4, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_init, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
+        hipLaunchKernelGGL(k_seed, dim3((nb + THREADS - 1) / THREADS), dim3(THREADS), 0, s, *g, nb);
+        RCHK(hipGetLastError());
+        // rounds until the frontier is empty; the host looks at the sizes
+        // every ROUNDS rounds (empty rounds cost a launch and nothing else)
+        constexpr int ROUNDS = 16;
+        int32_t cur = 0;
+        // each round settles at least one more hop of every shortest path,
+        // and a path has fewer than n_nodes hops; past that bound something
+        // is wrong (it cannot happen with finite positive costs)
+        const int64_t max_rounds = 2ll * n_nodes + 64;
+        for (int64_t rounds = 0;; rounds += ROUNDS) {
+            if (rounds > max_rounds) return LPSIM_EDEVICE;
+            for (int r = 0; r < ROUNDS; ++r) {
+                hipLaunchKernelGGL(k_relax, dim3(GRID), dim3(THREADS), 0, s, *g, cur);
+                hipLaunchKernelGGL(k_retire, dim3(GRID), dim3(THREADS), 0, s, *g, cur);
+                hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, s, *g, cur);
+                cur ^= 1;
+            }
+            RCHK(hipGetLastError());
+            uint32_t cnt[2] = {0, 0};
+            RCHK(hipMemcpyAsync(cnt, g->count, sizeof cnt, hipMemcpyDeviceToHost, s));
+            RCHK(hipStreamSynchronize(s));
+            if (cnt[cur] == 0) break;
+        }
+        hipLaunchKernelGGL(k_ties, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
+        RCHK(hipGetLastError());
+        RCHK(hipMemcpyAsync(next_edge + (size_t)d0 * n_nodes, g->nx, (size_t)nb * n_nodes * 4, hipMemcpyDeviceToHost,
+                            s));
+    }
+    return status(hipStreamSynchronize(s));
+}
+
+}  // namespace lpsim_route

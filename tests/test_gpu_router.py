@@ -1,0 +1,82 @@
+"""The routing step's GPU solve (lpsim_router_solve_gpu) against the host
+solve (lpsim_router_solve): the same trees, so the same routes, trip by
+trip and edge by edge, on grids and planar graphs, with free-flow costs,
+random costs and integer costs full of ties, at the size of the regional
+workload's 500 destinations; and route costs equal to an independent
+Dijkstra (scipy) where the check applies."""
+import numpy as np
+import pytest
+
+from paper_2406_08496_amd import synth
+from paper_2406_08496_amd.assign import Router
+from paper_2406_08496_amd.lpsim import LpsimError
+
+from test_gpu_parity import case
+from test_router import check_routes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def both(inst, cost, o, d, old=None, take_new=None):
+    host = Router(inst.n_nodes, inst.src, inst.dst, n_threads=8)
+    gpu = Router(inst.n_nodes, inst.src, inst.dst, gpu=True)
+    a = host.routes(cost, o, d, old=old, take_new=take_new)
+    b = gpu.routes(cost, o, d, old=old, take_new=take_new)
+    return a, b
+
+
+def assert_same_routes(a, b, what):
+    assert np.array_equal(a[0], b[0]), f"{what}: route offsets differ"
+    bad = np.nonzero(a[1] != b[1])[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} route entries differ, first at {bad[:5]}"
+
+
+@pytest.mark.parametrize("kind", ["free", "random", "ties"])
+def test_gpu_trees_equal_host_grid(torch, kind):
+    inst = synth.grid_instance(seed=6, side=9, n_trips=1500)
+    rng = np.random.default_rng(3)
+    base = inst.length.astype(np.float64) / inst.speed.astype(np.float64)
+    cost = {"free": base, "random": base * rng.uniform(0.5, 4.0, size=inst.n_edges),
+            "ties": rng.integers(1, 4, size=inst.n_edges).astype(np.float64)}[kind]
+    case("GPU trees vs host trees on a 9x9 grid,", kind, "costs")
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    a, b = both(inst, cost, o, d)
+    assert_same_routes(a, b, kind)
+    check_routes(inst, cost, o, d, *b)
+
+
+def test_gpu_trees_equal_host_regional(torch):
+    """The regional network at full size with its 500 destinations and
+    congested-looking costs; the solve also keeps the old routes where
+    asked."""
+    inst = synth.regional()
+    rng = np.random.default_rng(11)
+    cost = inst.length.astype(np.float64) / inst.speed.astype(np.float64)
+    cost = cost * np.exp(rng.normal(0.0, 1.0, size=inst.n_edges))
+    n = 200_000
+    o, d = inst.meta["origin"][:n], inst.meta["dest"][:n]
+    case("GPU trees vs host trees, regional network,", len(np.unique(d)), "destinations,", n, "trips")
+    old = (inst.route_off[:n + 1], inst.route_edges[:inst.route_off[n]])
+    take = (np.arange(n) % 3 == 0).astype(np.uint8)
+    a, b = both(inst, cost, o, d, old=old, take_new=take)
+    assert_same_routes(a, b, "regional")
+
+
+def test_gpu_unreachable_is_an_error(torch):
+    # 0 -> 1 -> 2 and nothing back: no route from 2 to 0
+    src = np.array([0, 1], np.int32)
+    dst = np.array([1, 2], np.int32)
+    r = Router(3, src, dst, gpu=True)
+    with pytest.raises(LpsimError):
+        r.routes(np.array([1.0, 2.0]), np.array([2], np.int32), np.array([0], np.int32))
+    off, edges = r.routes(np.array([1.0, 2.0]), np.array([0], np.int32), np.array([2], np.int32))
+    assert list(edges) == [0, 1]
