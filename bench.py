@@ -534,11 +534,13 @@ def run_assignment(inst, n_iter):
     a.progress = lambda r: log("plain", json.dumps(r))
     plain = a.run_plain(n_iter)
     log(f"plain MSA: {plain['wall_s']:.1f} s, timings {a.timings}")
+    t_plain = {k: round(v, 2) for k, v in a.timings.items()}
     del a
     b = Assignment(inst, n_bins=48, n_threads=16)
     b.progress = lambda r: log("surrogate", json.dumps(r))
     sur = b.run_surrogate(n_iter)
     log(f"surrogate MSA: {sur['wall_s']:.1f} s, timings {b.timings}")
+    t_sur = {k: round(v, 2) for k, v in b.timings.items()}
     w = plain["exits"].astype(np.float64)
     mean_rel, rel_l2 = edge_tt_errors(sur["tt"], plain["tt"], w)
     ttt_p = float((w * plain["tt"]).sum())
@@ -547,7 +549,9 @@ def run_assignment(inst, n_iter):
             "speedup": plain["wall_s"] / sur["wall_s"], "full_simulations": {"plain": n_iter, "surrogate": sur["n_sim"]},
             "final_tt_mean_rel": mean_rel, "final_tt_rel_l2": rel_l2,
             "total_travel_time_rel": ttt_s / ttt_p - 1.0,
-            "judge_errors": [h["judge_err"] for h in sur["hist"] if "judge_err" in h]}
+            "judge_errors": [h["judge_err"] for h in sur["hist"] if "judge_err" in h],
+            "timings_s": {"plain": t_plain, "surrogate": t_sur},
+            "router": "gpu"}
 
 
 if __name__ == "__main__":

@@ -400,6 +400,24 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
 int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
                                const int32_t *dest, void *stream);
 
+/* The method of successive averages' deterministic switch: take[i] = 1
+ * iff SplitMix64(seed ^ (i << 8) ^ n) mod (n + 1) == 0, so about 1/(n+1)
+ * of the trips move to their new route at iteration n (1-based).  Host
+ * buffer of n_trips.  Errors: EINVAL. */
+int32_t lpsim_msa_switch(int64_t n_trips, int32_t n, uint64_t seed, uint8_t *take);
+
+/* Routing cost of each edge from the statistics (lpsim_edge_stats): mean
+ * travel time tt_sum_steps / n_exits, or tt_free_steps where nothing
+ * exited, at least one step, times dt, in seconds (host arrays). */
+int32_t lpsim_edge_tt(int32_t n_edges, const int64_t *tt_sum_steps, const int32_t *n_exits,
+                      const double *tt_free_steps, double dt, double *out_s);
+
+/* Mean travel time per (edge, bin) in steps, [E][B] float32: tt_sum_bin /
+ * exits_bin in float64 rounded once, or the edge's tt_free_steps where no
+ * traversal entered in the bin (host arrays). */
+int32_t lpsim_edge_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum_bin, const int32_t *exits_bin,
+                           const double *tt_free_steps, float *out_steps);
+
 /* Write the routes of the last solve (host buffers).  take_new (n_trips
  * flags) NULL takes every new route; otherwise trip i keeps its old route
  * (old_off / old_edges) where take_new[i] == 0.  out_off receives n_trips+1

@@ -23,7 +23,6 @@ import numpy as np
 
 from .lpsim import LpsimError, Simulator, load_library
 
-MASK64 = (1 << 64) - 1
 WIN = 12  # statistics bins per perceptron sample
 
 
@@ -31,21 +30,15 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def mix64(z):
-    """SplitMix64 output function (Steele, Lea & Flood 2014), uint64 arrays."""
-    z = np.asarray(z, dtype=np.uint64)
-    with np.errstate(over="ignore"):
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-    return z ^ (z >> np.uint64(31))
-
-
 def msa_switch(n_trips, n, seed):
     """Trip i moves to its new route at iteration n (1-based) iff
-    mix64(seed ^ i<<8 ^ n) mod (n+1) == 0: a deterministic 1/(n+1) share."""
-    i = np.arange(n_trips, dtype=np.uint64)
-    h = mix64(np.uint64(seed) ^ (i << np.uint64(8)) ^ np.uint64(n))
-    return (h % np.uint64(n + 1) == 0).astype(np.uint8)
+    mix64(seed ^ i<<8 ^ n) mod (n+1) == 0: a deterministic 1/(n+1) share
+    (lpsim_msa_switch)."""
+    take = np.empty(n_trips, np.uint8)
+    rc = load_library().lpsim_msa_switch(int(n_trips), int(n), ctypes.c_uint64(seed & ((1 << 64) - 1)), _p(take))
+    if rc:
+        raise LpsimError(rc, "msa switch")
+    return take
 
 
 class Router:
@@ -108,7 +101,7 @@ class Assignment:
     """One MSA run on an instance; `evaluate` is the full simulation or the
     surrogate depending on the mode."""
 
-    def __init__(self, inst, n_bins=48, seed=0xA55, sim_params=None, n_threads=0, horizon=None):
+    def __init__(self, inst, n_bins=48, seed=0xA55, sim_params=None, n_threads=0, horizon=None, gpu_router=True):
         import torch
 
         self.torch = torch
@@ -121,7 +114,7 @@ class Assignment:
                               node_xy=inst.node_xy)
         self.dt = float(self.sim.params["dt"])
         self.bin_steps = int(round(self.sim.params["bin_seconds"] / self.dt))
-        self.router = Router(inst.n_nodes, inst.src, inst.dst, n_threads=n_threads)
+        self.router = Router(inst.n_nodes, inst.src, inst.dst, n_threads=n_threads, gpu=gpu_router)
         self.tt_free = free_flow_steps(inst, self.dt)
         self.origin = inst.meta["origin"]
         self.dest = inst.meta["dest"]
@@ -129,19 +122,34 @@ class Assignment:
         self.progress = None  # optional callable(dict) after each iteration
 
     # -- evaluation by simulation -------------------------------------------
-    def simulate(self, off, edges):
+    def simulate(self, off, edges, binned=True):
+        """Full simulation of the routes; binned statistics only if asked
+        (the surrogate needs them, the plain loop does not)."""
         t0 = time.perf_counter()
         self.sim.load_trips(self.inst.depart_step, off, edges)
+        t1 = time.perf_counter()
         self.sim.step(self.horizon)
-        st = self.sim.edge_stats()
-        self._add("simulate", time.perf_counter() - t0)
+        self.torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = self.sim.edge_stats(binned=binned)
+        t3 = time.perf_counter()
+        self._add("simulate", t3 - t0)
+        self._add("sim_load", t1 - t0)
+        self._add("sim_step", t2 - t1)
+        self._add("sim_stats", t3 - t2)
         return st
 
     def edge_tt_from_stats(self, st):
-        """Mean simulated travel time per edge in seconds (free flow if unused)."""
-        n = st["n_exits"].astype(np.float64)
-        mean = np.where(n > 0, st["tt_sum"] / np.maximum(n, 1), self.tt_free)
-        return np.maximum(mean, 1.0) * self.dt
+        """Mean simulated travel time per edge in seconds, free flow if
+        unused (lpsim_edge_tt)."""
+        out = np.empty(self.inst.n_edges, np.float64)
+        tf = np.ascontiguousarray(self.tt_free, np.float64)
+        rc = load_library().lpsim_edge_tt(self.inst.n_edges, _p(np.ascontiguousarray(st["tt_sum"], np.int64)),
+                                          _p(np.ascontiguousarray(st["n_exits"], np.int32)), _p(tf),
+                                          ctypes.c_double(self.dt), _p(out))
+        if rc:
+            raise LpsimError(rc, "edge tt")
+        return out
 
     def _add(self, k, v):
         self.timings[k] = self.timings.get(k, 0.0) + v
@@ -163,13 +171,13 @@ class Assignment:
         off, edges = self.inst.route_off, self.inst.route_edges
         hist = []
         for n in range(1, n_iter + 1):
-            st = self.simulate(off, edges)
+            st = self.simulate(off, edges, binned=False)
             tt = self.edge_tt_from_stats(st)
             hist.append({"n": n, "mode": "sim", "mean_tt": float(np.average(tt, weights=st["n_exits"] + 1e-9))})
             self._progress(hist[-1], t0)
             off, edges = self.reroute(tt, off, edges, n)
         wall = time.perf_counter() - t0
-        st = self.simulate(off, edges)
+        st = self.simulate(off, edges, binned=False)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
                 "routes": (off, edges)}
 
@@ -287,9 +295,15 @@ class Assignment:
     def tt_bins_from_stats(self, st):
         """Per-(edge, bin) mean travel time in steps, free flow where no
         traversal entered (device, float32)."""
-        ttb = st["tt_bin"] / np.maximum(st["exits_bin"], 1)
-        return self.torch.from_numpy(np.where(st["exits_bin"] > 0, ttb,
-                                              self.tt_free[:, None]).astype(np.float32)).to("cuda")
+        E, B = st["tt_bin"].shape
+        out = np.empty((E, B), np.float32)
+        tf = np.ascontiguousarray(self.tt_free, np.float64)
+        rc = load_library().lpsim_edge_tt_bins(E, B, _p(np.ascontiguousarray(st["tt_bin"], np.int64)),
+                                               _p(np.ascontiguousarray(st["exits_bin"], np.int32)), _p(tf),
+                                               _p(out))
+        if rc:
+            raise LpsimError(rc, "edge tt bins")
+        return self.torch.from_numpy(out).to("cuda")
 
     # -- surrogate-assisted MSA -------------------------------------------------
     def run_surrogate(self, n_iter, judge_every=5, tol=0.05, train_steps=300, batch=8192, lr=2e-3,
@@ -369,7 +383,7 @@ class Assignment:
                 self._progress(hist[-1], t0)
             off, edges = self.reroute(tt, off, edges, n)
         wall = time.perf_counter() - t0
-        st = self.simulate(off, edges)
+        st = self.simulate(off, edges, binned=False)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
                 "routes": (off, edges), "n_sim": sum(1 for h in hist if h["mode"] == "sim")}
 

@@ -42,7 +42,12 @@ struct lpsim_router {
     std::vector<int32_t> dests;      // distinct destination nodes
     std::vector<int32_t> dest_idx;   // per trip
     std::vector<int32_t> origin;     // per trip
-    std::vector<int32_t> next_edge;  // [dest][node]
+    // tree edge per [dest][node] of the last solve: a host vector for host
+    // solves, page-locked memory (the GPU copies into it) for GPU solves
+    std::vector<int32_t> nx_vec;
+    int32_t *nx_pinned = nullptr;
+    size_t nx_pinned_cap = 0;
+    int32_t *next_edge = nullptr;
     std::vector<int32_t> len;        // per trip, new route length (trips taking one)
     bool solved = false;
     lpsim_route::GpuRouter *gpu = nullptr;  // device copy of the graph (GPU solves)
@@ -143,6 +148,7 @@ int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src
 void lpsim_router_destroy(lpsim_router *r) {
     if (!r) return;
     lpsim_route::gpu_router_free(r->gpu);
+    if (r->nx_pinned) (void)hipHostFree(r->nx_pinned);
     delete r;
 }
 
@@ -155,7 +161,8 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
         if (!(cost[e] > 0.0) || !std::isfinite(cost[e])) return LPSIM_EINVAL;
     r->solved = false;
     try {
-        std::unordered_map<int32_t, int32_t> idx;
+        // distinct destinations in order of first appearance
+        std::vector<int32_t> idx((size_t)r->n_nodes, -1);
         r->dests.clear();
         r->dest_idx.resize((size_t)n_trips);
         r->origin.assign(origin, origin + n_trips);
@@ -163,19 +170,37 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
             const int32_t t = dest[i];
             if (t < 0 || t >= r->n_nodes || origin[i] < 0 || origin[i] >= r->n_nodes || origin[i] == t)
                 return LPSIM_EINVAL;
-            auto it = idx.find(t);
-            if (it == idx.end()) {
-                it = idx.emplace(t, (int32_t)r->dests.size()).first;
+            if (idx[(size_t)t] < 0) {
+                idx[(size_t)t] = (int32_t)r->dests.size();
                 r->dests.push_back(t);
             }
-            r->dest_idx[(size_t)i] = it->second;
+            r->dest_idx[(size_t)i] = idx[(size_t)t];
         }
         const int32_t nd = (int32_t)r->dests.size();
-        r->next_edge.assign((size_t)nd * r->n_nodes, -1);
+        // every entry is written by the solve (-1 where there is no tree edge)
+        const size_t nx_n = (size_t)nd * r->n_nodes;
+        if (on_gpu) {
+            if (r->nx_pinned_cap < nx_n) {
+                if (r->nx_pinned) (void)hipHostFree(r->nx_pinned);
+                r->nx_pinned = nullptr;
+                r->nx_pinned_cap = 0;
+                if (hipHostMalloc((void **)&r->nx_pinned, std::max<size_t>(nx_n, 1) * 4, hipHostMallocDefault) !=
+                    hipSuccess) {
+                    (void)hipGetLastError();
+                    r->nx_pinned = nullptr;
+                    return LPSIM_ENOMEM;
+                }
+                r->nx_pinned_cap = nx_n;
+            }
+            r->next_edge = r->nx_pinned;
+        } else {
+            if (r->nx_vec.size() < nx_n) r->nx_vec.resize(nx_n);
+            r->next_edge = r->nx_vec.data();
+        }
         if (on_gpu) {
             const int32_t rc = lpsim_route::gpu_router_solve(
                 &r->gpu, r->n_nodes, r->n_edges, r->in_off.data(), r->in_edges.data(), r->in_src.data(),
-                r->src.data(), r->dst.data(), cost, r->dests.data(), nd, r->next_edge.data(), (hipStream_t)stream);
+                r->src.data(), r->dst.data(), cost, r->dests.data(), nd, r->next_edge, (hipStream_t)stream);
             if (rc) return rc;
         }
         r->in_cost.resize(r->in_edges.size());
@@ -189,7 +214,7 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
             for (;;) {
                 const int32_t d = next.fetch_add(1);
                 if (d >= nd) break;
-                tree_to(*r, cost, r->dests[(size_t)d], r->next_edge.data() + (size_t)d * r->n_nodes, dist[w],
+                tree_to(*r, cost, r->dests[(size_t)d], r->next_edge + (size_t)d * r->n_nodes, dist[w],
                         done[w], heap[w]);
             }
         };
@@ -218,6 +243,43 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
     return router_solve(r, cost, n_trips, origin, dest, false, nullptr);
 }
 
+int32_t lpsim_msa_switch(int64_t n_trips, int32_t n, uint64_t seed, uint8_t *take) {
+    if (n_trips < 0 || n < 1 || (n_trips > 0 && !take)) return LPSIM_EINVAL;
+    auto mix = [](uint64_t z) {  // SplitMix64 output function
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    for (int64_t i = 0; i < n_trips; ++i)
+        take[i] = mix(seed ^ ((uint64_t)i << 8) ^ (uint64_t)n) % (uint64_t)(n + 1) == 0 ? 1 : 0;
+    return LPSIM_OK;
+}
+
+int32_t lpsim_edge_tt(int32_t n_edges, const int64_t *tt_sum_steps, const int32_t *n_exits,
+                      const double *tt_free_steps, double dt, double *out_s) {
+    if (n_edges < 0 || !(dt > 0) || (n_edges > 0 && (!tt_sum_steps || !n_exits || !tt_free_steps || !out_s)))
+        return LPSIM_EINVAL;
+    for (int32_t e = 0; e < n_edges; ++e) {
+        const double mean = n_exits[e] > 0 ? (double)tt_sum_steps[e] / (double)n_exits[e] : tt_free_steps[e];
+        out_s[e] = (mean > 1.0 ? mean : 1.0) * dt;
+    }
+    return LPSIM_OK;
+}
+
+int32_t lpsim_edge_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum_bin, const int32_t *exits_bin,
+                           const double *tt_free_steps, float *out_steps) {
+    if (n_edges < 0 || n_bins < 1 ||
+        (n_edges > 0 && (!tt_sum_bin || !exits_bin || !tt_free_steps || !out_steps)))
+        return LPSIM_EINVAL;
+    for (int64_t e = 0; e < n_edges; ++e)
+        for (int64_t b = 0; b < n_bins; ++b) {
+            const int64_t i = e * n_bins + b;
+            out_steps[i] = exits_bin[i] > 0 ? (float)((double)tt_sum_bin[i] / (double)exits_bin[i])
+                                            : (float)tt_free_steps[e];
+        }
+    return LPSIM_OK;
+}
+
 int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
                                const int32_t *dest, void *stream) {
     return router_solve(r, cost, n_trips, origin, dest, true, stream);
@@ -237,7 +299,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
         parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
             for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
                 if (take_new && !take_new[i]) continue;
-                const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+                const int32_t *nx = r->next_edge + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
                 const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
                 int32_t u = r->origin[(size_t)i], l = 0;
                 while (u != t && l <= r->n_nodes) {
@@ -262,7 +324,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
                 std::memcpy(o, old_edges + old_off[i], (size_t)(old_off[i + 1] - old_off[i]) * 4);
                 continue;
             }
-            const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+            const int32_t *nx = r->next_edge + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
             const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
             int32_t u = r->origin[(size_t)i];
             while (u != t) {

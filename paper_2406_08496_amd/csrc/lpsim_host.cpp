@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -10,6 +11,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lpsim.h"
@@ -409,6 +411,27 @@ static int32_t reset_run_state(lpsim_ctx *c) {
     return LPSIM_OK;
 }
 
+// f(begin, end) over [0, n) in chunks on the host's hardware threads
+template <class F>
+static void host_parallel(int64_t n, F &&f) {
+    const int64_t chunk = 1 << 16;
+    const int64_t n_chunks = (n + chunk - 1) / chunk;
+    const int32_t nt = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(n_chunks, std::min<unsigned>(32u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::atomic<int64_t> next{0};
+    auto worker = [&]() {
+        for (;;) {
+            const int64_t ci = next.fetch_add(1);
+            if (ci >= n_chunks) break;
+            f(ci * chunk, std::min(n, (ci + 1) * chunk));
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &t : pool) t.join();
+}
+
 static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if (!c->have_net) return fail(c, LPSIM_ESTATE, "load a network first");
     const int32_t S = c->n_scen;
@@ -433,13 +456,32 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         }
         const int64_t len = ro[nt];
         const int32_t *re = in.route_edges + total;
-        for (int64_t t = 0; t < nt; ++t) {
-            for (int64_t j = ro[t]; j < ro[t + 1]; ++j) {
-                const int32_t e = re[j];
-                if (e < 0 || e >= ne) return fail(c, LPSIM_EINVAL, "trip %lld: edge id out of range", (long long)(t0 + t));
-                if (j > ro[t] && c->dst_g[eb + re[j - 1]] != c->src_g[eb + e])
-                    return fail(c, LPSIM_EINVAL, "trip %lld: route is not contiguous", (long long)(t0 + t));
+        // edge ids in range and routes contiguous, checked on all host
+        // threads; the lowest failing trip is reported
+        std::atomic<int64_t> bad_range{INT64_MAX}, bad_gap{INT64_MAX};
+        host_parallel(nt, [&](int64_t t_lo, int64_t t_hi) {
+            for (int64_t t = t_lo; t < t_hi; ++t) {
+                for (int64_t j = ro[t]; j < ro[t + 1]; ++j) {
+                    const int32_t e = re[j];
+                    if (e < 0 || e >= ne) {
+                        int64_t cur = bad_range.load();
+                        while (t < cur && !bad_range.compare_exchange_weak(cur, t)) {
+                        }
+                        break;
+                    }
+                    if (j > ro[t] && c->dst_g[eb + re[j - 1]] != c->src_g[eb + e]) {
+                        int64_t cur = bad_gap.load();
+                        while (t < cur && !bad_gap.compare_exchange_weak(cur, t)) {
+                        }
+                        break;
+                    }
+                }
             }
+        });
+        if (bad_range.load() != INT64_MAX || bad_gap.load() != INT64_MAX) {
+            if (bad_range.load() <= bad_gap.load())
+                return fail(c, LPSIM_EINVAL, "trip %lld: edge id out of range", (long long)(t0 + bad_range.load()));
+            return fail(c, LPSIM_EINVAL, "trip %lld: route is not contiguous", (long long)(t0 + bad_gap.load()));
         }
         total += (uint64_t)len;
         if (total > 0xfffffff0ull) return fail(c, LPSIM_ECAPACITY, "more than 2^32-16 route entries");
@@ -455,7 +497,11 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
             const int64_t nt = in.trip_off[s + 1] - in.trip_off[s];
             const int32_t eb = c->edge_off[s];
             const int64_t len = ro2[nt];
-            for (int64_t j = 0; j < len; ++j) route[p + (size_t)j] = (uint32_t)c->int_of_ext[eb + in.route_edges[p + (size_t)j]];
+            const int32_t *re = in.route_edges + p;
+            uint32_t *out = route.data() + p;
+            host_parallel(len, [&](int64_t lo, int64_t hi) {
+                for (int64_t j = lo; j < hi; ++j) out[j] = (uint32_t)c->int_of_ext[eb + re[j]];
+            });
             p += (size_t)len;
             ro2 += nt + 1;
         }
@@ -485,16 +531,19 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         std::vector<uint4> rec_h(c->n_edges);
         HIPCHK(c, hipMemcpy(rec_h.data(), c->d.edge, (size_t)c->n_edges * 16, hipMemcpyDeviceToHost));
         for (int32_t s = 0; s < S; ++s) {
-            for (int64_t t = in.trip_off[s]; t < in.trip_off[s + 1]; ++t) {
-                const uint32_t r0 = roff[(size_t)t];
-                const uint32_t e0 = route[r0];
-                const uint4 R = rec_h[e0];
-                const uint32_t C = R.y & 0xffffu, nl = (R.y >> 16) & 0xffu;
-                const uint32_t l0 = (uint32_t)(t - in.trip_off[s]) % nl;
-                orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, r0);
-                const uint32_t rend = roff[(size_t)t + 1];
-                dep_rec[(size_t)t] = make_uint4(r0, rend, r0 + 1 < rend ? route[r0 + 1] : NO_NEXT, 0u);
-            }
+            const int64_t t0 = in.trip_off[s];
+            host_parallel(in.trip_off[s + 1] - t0, [&](int64_t lo, int64_t hi) {
+                for (int64_t t = t0 + lo; t < t0 + hi; ++t) {
+                    const uint32_t r0 = roff[(size_t)t];
+                    const uint32_t e0 = route[r0];
+                    const uint4 R = rec_h[e0];
+                    const uint32_t C = R.y & 0xffffu, nl = (R.y >> 16) & 0xffu;
+                    const uint32_t l0 = (uint32_t)(t - t0) % nl;
+                    orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, r0);
+                    const uint32_t rend = roff[(size_t)t + 1];
+                    dep_rec[(size_t)t] = make_uint4(r0, rend, r0 + 1 < rend ? route[r0 + 1] : NO_NEXT, 0u);
+                }
+            });
         }
     }
     std::vector<uint64_t> seeds(S);

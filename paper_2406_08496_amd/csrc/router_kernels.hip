@@ -10,9 +10,18 @@
 // distance dropped relaxes the in-edges of its node with a 64-bit atomic
 // minimum on the distance bits (non-negative doubles order like their bit
 // patterns), and every drop queues the upstream pair once.  The fixed point
-// is unique, so the order of relaxations does not change it.  The tree
-// edges are then picked in a separate pass that compares each out-edge's
-// candidate with the final distance, exactly as the Dijkstra's tie rule does.
+// is unique, so the order of relaxations does not change it.
+//
+// Relaxing in hop order alone settles a pair many times over (about 23
+// times on the regional network with congested costs), so the frontier is
+// split by distance (near-far, Davidson et al. 2014): a round relaxes only
+// pairs at most a threshold tau from their destination; drops above tau wait
+// in a far pile, and when the near frontier runs dry tau moves up by delta
+// (or to the nearest waiting pair) and the far pile is split again.
+//
+// The tree edges are then picked in a separate pass that compares each
+// out-edge's candidate with the final distance, exactly as the Dijkstra's
+// tie rule does.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,6 +37,7 @@ constexpr unsigned long long INF_BITS = 0x7ff0000000000000ull;  // +infinity
 constexpr int THREADS = 256;
 constexpr int GRID = 2048;         // blocks of the grid-stride kernels
 constexpr int PUSH_BUF = 4 * THREADS;  // per-block staging of queued pairs
+constexpr double DELTA_COSTS = 16.0;    // near-far threshold step, in mean edge costs
 
 struct GpuRouter {
     int32_t n = 0, m = 0;
@@ -41,9 +51,14 @@ struct GpuRouter {
     unsigned long long *dist = nullptr;
     uint2 *front[2] = {nullptr, nullptr};
     uint32_t *flags[2] = {nullptr, nullptr};  // one bit per pair
-    uint32_t *count = nullptr;                // [2] frontier sizes
+    uint32_t *count = nullptr;                // [3] frontier sizes, by round mod 3
     int32_t *targets = nullptr;
     int32_t *nx = nullptr;
+    // far pile: pairs whose distance dropped above the threshold
+    uint2 *far[2] = {nullptr, nullptr};
+    uint32_t *far_flags = nullptr;             // one bit per pair in the pile
+    uint32_t *far_count = nullptr;             // [2]
+    unsigned long long *far_min = nullptr;     // least distance bits entering the pile
     std::vector<void *> allocs;
 };
 
@@ -63,6 +78,7 @@ __global__ void k_init(GpuRouter g, int32_t nd) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x) {
         g.flags[0][i] = 0;
         g.flags[1][i] = 0;
+        g.far_flags[i] = 0;
     }
 }
 
@@ -76,26 +92,75 @@ __global__ void k_seed(GpuRouter g, int32_t nd) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         g.count[0] = (uint32_t)nd;
         g.count[1] = 0;
+        g.count[2] = 0;
+        g.far_count[0] = 0;
+        g.far_count[1] = 0;
+        *g.far_min = ~0ull;
     }
 }
 
-// one round: every queued pair relaxes the in-edges of its node; pairs whose
-// distance drops are queued (once) for the next round
-__global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t cur) {
-    __shared__ uint2 buf[PUSH_BUF];
-    __shared__ uint32_t n_buf, base;
-    const uint32_t nf = g.count[cur];
+// queue of one block's pushes, flushed into a list with one atomic
+struct PushBuf {
+    uint2 item[PUSH_BUF / 2];
+    uint32_t n, base;
+};
+
+__device__ __forceinline__ void push(PushBuf &b, uint2 *list, uint32_t *count, uint2 it) {
+    const uint32_t k = atomicAdd(&b.n, 1u);
+    if (k < PUSH_BUF / 2) b.item[k] = it;
+    else list[atomicAdd(count, 1u)] = it;
+}
+
+__device__ __forceinline__ void flush(PushBuf &b, uint2 *list, uint32_t *count) {
+    const uint32_t nb = b.n < PUSH_BUF / 2 ? b.n : PUSH_BUF / 2;
+    if (threadIdx.x == 0 && nb) b.base = atomicAdd(count, nb);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) list[b.base + k] = b.item[k];
+}
+
+// least of the block's values, then one atomic for the block
+__device__ __forceinline__ void block_min(unsigned long long v, unsigned long long *dst, unsigned long long *s_min) {
+    if (v != ~0ull) atomicMin(s_min, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && *s_min != ~0ull) atomicMin(dst, *s_min);
+}
+
+// round r: every queued pair of near frontier r % 2 relaxes the in-edges of
+// its node; a drop to at most tau queues the upstream pair (once) in the
+// other near frontier, a drop above tau puts it (once) in the far pile.  A
+// processed pair's queue flag is cleared here (nothing queues into this
+// round's frontier during the round), and the size counter of round r + 2 is
+// reset (round r - 1, its last reader, has finished).
+__global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t round, double tau, int32_t fc) {
+    __shared__ PushBuf bn, bf;
+    __shared__ unsigned long long s_min;
+    const int32_t cur = round & 1;
+    const uint32_t nf = g.count[round % 3];
     const uint2 *front = g.front[cur];
+    uint32_t *flags = g.flags[cur];
     uint2 *next = g.front[cur ^ 1];
     uint32_t *nflags = g.flags[cur ^ 1];
-    uint32_t *ncount = &g.count[cur ^ 1];
+    uint32_t *ncount = &g.count[(round + 1) % 3];
+    const unsigned long long tau_b = (unsigned long long)__double_as_longlong(tau);
+    if (blockIdx.x == 0 && threadIdx.x == 0) g.count[(round + 2) % 3] = 0;
     for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < nf; t0 += gridDim.x * blockDim.x) {
-        if (threadIdx.x == 0) n_buf = 0;
+        if (threadIdx.x == 0) {
+            bn.n = 0;
+            bf.n = 0;
+            s_min = ~0ull;
+        }
         __syncthreads();
+        unsigned long long fmin = ~0ull;
         const uint32_t t = t0 + threadIdx.x;
         if (t < nf) {
             const uint2 it = front[t];
             const size_t row = (size_t)it.x * g.n;
+            {
+                // leaves the queue; other pairs of the same flag word are in
+                // this frontier too, so the word can simply be cleared
+                const size_t pair = row + it.y;
+                flags[pair >> 5] = 0u;
+            }
             unsigned long long *dd = g.dist + row;
             const double dy = __longlong_as_double((long long)dd[it.y]);
             for (int32_t j = g.in_off[it.y]; j < g.in_off[it.y + 1]; ++j) {
@@ -106,36 +171,65 @@ __global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t cur) {
                 if (cb >= old) continue;
                 const size_t pair = row + (size_t)x;
                 const uint32_t bit = 1u << (pair & 31);
-                if (atomicOr(&nflags[pair >> 5], bit) & bit) continue;  // already queued
-                const uint32_t k = atomicAdd(&n_buf, 1u);
-                if (k < PUSH_BUF) {
-                    buf[k] = make_uint2(it.x, (uint32_t)x);
+                if (cb <= tau_b) {
+                    if (atomicOr(&nflags[pair >> 5], bit) & bit) continue;  // already queued
+                    push(bn, next, ncount, make_uint2(it.x, (uint32_t)x));
                 } else {
-                    next[atomicAdd(ncount, 1u)] = make_uint2(it.x, (uint32_t)x);
+                    fmin = cb < fmin ? cb : fmin;
+                    if (atomicOr(&g.far_flags[pair >> 5], bit) & bit) continue;  // already in the pile
+                    push(bf, g.far[fc], &g.far_count[fc], make_uint2(it.x, (uint32_t)x));
                 }
             }
         }
         __syncthreads();
-        const uint32_t nb = n_buf < PUSH_BUF ? n_buf : PUSH_BUF;
-        if (threadIdx.x == 0 && nb) base = atomicAdd(ncount, nb);
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) next[base + k] = buf[k];
+        flush(bn, next, ncount);
+        flush(bf, g.far[fc], &g.far_count[fc]);
+        block_min(fmin, g.far_min, &s_min);
         __syncthreads();
     }
 }
 
-// after a round: the processed frontier's flags are cleared and its count
-// reset, so the buffer can take the round after next
-__global__ void k_retire(GpuRouter g, int32_t cur) {
-    const uint32_t nf = g.count[cur];
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nf; t += gridDim.x * blockDim.x) {
-        const uint2 it = g.front[cur][t];
-        const size_t pair = (size_t)it.x * g.n + it.y;
-        g.flags[cur][pair >> 5] = 0u;
+// the near frontier ran dry: the far pile (buffer fc) is split by the new
+// threshold tau; pairs now within it join the next near frontier (round r +
+// 1), the others move to pile fc ^ 1, whose least distance is recorded
+__global__ __launch_bounds__(THREADS) void k_split(GpuRouter g, int32_t round, double tau, int32_t fc) {
+    __shared__ PushBuf bn, bf;
+    __shared__ unsigned long long s_min;
+    const int32_t nxt = (round + 1) & 1;
+    uint2 *next = g.front[nxt];
+    uint32_t *nflags = g.flags[nxt];
+    uint32_t *ncount = &g.count[(round + 1) % 3];
+    const uint32_t nfar = g.far_count[fc];
+    const unsigned long long tau_b = (unsigned long long)__double_as_longlong(tau);
+    for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < nfar; t0 += gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) {
+            bn.n = 0;
+            bf.n = 0;
+            s_min = ~0ull;
+        }
+        __syncthreads();
+        unsigned long long fmin = ~0ull;
+        const uint32_t t = t0 + threadIdx.x;
+        if (t < nfar) {
+            const uint2 it = g.far[fc][t];
+            const size_t pair = (size_t)it.x * g.n + it.y;
+            const uint32_t bit = 1u << (pair & 31);
+            const unsigned long long db = g.dist[pair];
+            if (db <= tau_b) {
+                atomicAnd(&g.far_flags[pair >> 5], ~bit);
+                if (!(atomicOr(&nflags[pair >> 5], bit) & bit)) push(bn, next, ncount, it);
+            } else {
+                fmin = db;
+                push(bf, g.far[fc ^ 1], &g.far_count[fc ^ 1], it);
+            }
+        }
+        __syncthreads();
+        flush(bn, next, ncount);
+        flush(bf, g.far[fc ^ 1], &g.far_count[fc ^ 1]);
+        block_min(fmin, g.far_min, &s_min);
+        __syncthreads();
     }
 }
-
-__global__ void k_reset_count(GpuRouter g, int32_t cur) { g.count[cur] = 0; }
 
 // tree edge of every (destination, node): the lowest out-edge whose
 // candidate equals the node's distance (-1 at the destination or if the
@@ -219,7 +313,9 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         RCHK(alloc(g, g->in_cost, (size_t)n_edges));
         RCHK(alloc(g, g->out_cost, (size_t)n_edges));
         RCHK(alloc(g, g->cost, (size_t)n_edges));
-        RCHK(alloc(g, g->count, 2));
+        RCHK(alloc(g, g->count, 3));
+        RCHK(alloc(g, g->far_count, 2));
+        RCHK(alloc(g, g->far_min, 1));
         RCHK(hipMemcpy(g->in_off, io.data(), io.size() * 4, hipMemcpyHostToDevice));
         RCHK(hipMemcpy(g->in_src, in_src_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
         RCHK(hipMemcpy(g->in_edge, in_edges_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
@@ -229,8 +325,8 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
     }
     GpuRouter *g = *gp;
     if (g->n != n_nodes || g->m != n_edges) return LPSIM_EINVAL;
-    // destinations per batch: distances, frontiers and flags of at most 64M pairs
-    const int32_t per = std::max<int32_t>(1, std::min<int32_t>(nd, (int32_t)((64ll << 20) / n_nodes)));
+    // destinations per batch: distances, frontiers and flags of at most 256M pairs (about 7 GB)
+    const int32_t per = std::max<int32_t>(1, std::min<int32_t>(nd, (int32_t)((256ll << 20) / n_nodes)));
     const size_t pairs = (size_t)per * (size_t)n_nodes;
     if (g->cap_pairs < pairs) {
         // grow the batch buffers (freed with the router)
@@ -241,8 +337,16 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         RCHK(alloc(g, g->flags[1], (pairs + 31) / 32));
         RCHK(alloc(g, g->nx, pairs));
         RCHK(alloc(g, g->targets, (size_t)per));
+        RCHK(alloc(g, g->far[0], pairs));
+        RCHK(alloc(g, g->far[1], pairs));
+        RCHK(alloc(g, g->far_flags, (pairs + 31) / 32));
         g->cap_pairs = pairs;
     }
+    // threshold step of the near-far split: a few mean edge costs
+    double mean_cost = 0.0;
+    for (int32_t e = 0; e < n_edges; ++e) mean_cost += cost_h[e];
+    mean_cost /= std::max(1, n_edges);
+    const double delta = DELTA_COSTS * mean_cost;
     RCHK(hipMemcpyAsync(g->cost, cost_h, (size_t)n_edges * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_costs, dim3(GRID), dim3(THREADS), 0, s, *g);
     RCHK(hipGetLastError());
@@ -252,27 +356,43 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         hipLaunchKernelGGL(k_init, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
         hipLaunchKernelGGL(k_seed, dim3((nb + THREADS - 1) / THREADS), dim3(THREADS), 0, s, *g, nb);
         RCHK(hipGetLastError());
-        // rounds until the frontier is empty; the host looks at the sizes
-        // every ROUNDS rounds (empty rounds cost a launch and nothing else)
-        constexpr int ROUNDS = 16;
-        int32_t cur = 0;
-        // each round settles at least one more hop of every shortest path,
-        // and a path has fewer than n_nodes hops; past that bound something
-        // is wrong (it cannot happen with finite positive costs)
-        const int64_t max_rounds = 2ll * n_nodes + 64;
-        for (int64_t rounds = 0;; rounds += ROUNDS) {
+        // rounds until the near frontier and the far pile are both empty;
+        // the host reads the sizes after every round and moves the threshold
+        int32_t round = 0, fc = 0;
+        double tau = delta;
+        // each round settles at least one more hop of every shortest path
+        // within the threshold, and the threshold only rises; past this bound
+        // something is wrong (it cannot happen with finite positive costs)
+        const int64_t max_rounds = 4ll * n_nodes + 1024;
+        for (int64_t rounds = 0;; ++rounds) {
             if (rounds > max_rounds) return LPSIM_EDEVICE;
-            for (int r = 0; r < ROUNDS; ++r) {
-                hipLaunchKernelGGL(k_relax, dim3(GRID), dim3(THREADS), 0, s, *g, cur);
-                hipLaunchKernelGGL(k_retire, dim3(GRID), dim3(THREADS), 0, s, *g, cur);
-                hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, s, *g, cur);
-                cur ^= 1;
-            }
+            hipLaunchKernelGGL(k_relax, dim3(GRID), dim3(THREADS), 0, s, *g, round, tau, fc);
             RCHK(hipGetLastError());
-            uint32_t cnt[2] = {0, 0};
-            RCHK(hipMemcpyAsync(cnt, g->count, sizeof cnt, hipMemcpyDeviceToHost, s));
+            struct {
+                uint32_t count[3], far_count[2];
+                unsigned long long far_min;
+            } st;
+            RCHK(hipMemcpyAsync(st.count, g->count, sizeof st.count, hipMemcpyDeviceToHost, s));
+            RCHK(hipMemcpyAsync(st.far_count, g->far_count, sizeof st.far_count, hipMemcpyDeviceToHost, s));
+            RCHK(hipMemcpyAsync(&st.far_min, g->far_min, 8, hipMemcpyDeviceToHost, s));
             RCHK(hipStreamSynchronize(s));
-            if (cnt[cur] == 0) break;
+            if (st.count[(round + 1) % 3] == 0) {
+                if (st.far_count[fc] == 0) break;
+                // next threshold: one step up, or at once to the nearest
+                // waiting pair; the pile is split into the near frontier and
+                // the other pile
+                double fmin;
+                std::memcpy(&fmin, &st.far_min, 8);
+                tau = std::max(tau + delta, fmin);
+                const uint32_t zero = 0;
+                const unsigned long long inf = ~0ull;
+                RCHK(hipMemcpyAsync(&g->far_count[fc ^ 1], &zero, 4, hipMemcpyHostToDevice, s));
+                RCHK(hipMemcpyAsync(g->far_min, &inf, 8, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_split, dim3(GRID), dim3(THREADS), 0, s, *g, round, tau, fc);
+                RCHK(hipGetLastError());
+                fc ^= 1;
+            }
+            ++round;
         }
         hipLaunchKernelGGL(k_ties, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
         RCHK(hipGetLastError());

@@ -82,6 +82,9 @@ SIGNATURES = {
     "lpsim_router_destroy": ([_vp], None),
     "lpsim_router_solve": ([_vp, _vp, _i64, _vp, _vp], _i32),
     "lpsim_router_solve_gpu": ([_vp, _vp, _i64, _vp, _vp, _vp], _i32),
+    "lpsim_msa_switch": ([_i64, _i32, ctypes.c_uint64, _vp], _i32),
+    "lpsim_edge_tt": ([_i32, _vp, _vp, _vp, ctypes.c_double, _vp], _i32),
+    "lpsim_edge_tt_bins": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
     "lpsim_router_fill": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_load": ([_vp, _vp, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_features": ([_i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),

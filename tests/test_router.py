@@ -119,3 +119,46 @@ def test_fill_in_one_call():
     edges1 = np.zeros(len(edges2), np.int32)
     assert r.lib.lpsim_router_fill(r._h, vp(old[0]), vp(old[1]), vp(take), vp(off1), vp(edges1)) == 0
     assert np.array_equal(off1, off2) and np.array_equal(edges1, edges2)
+
+
+def test_msa_switch_definition():
+    """lpsim_msa_switch against its definition written out with Python
+    integers: SplitMix64 of seed ^ i << 8 ^ n, modulo n + 1."""
+    from paper_2406_08496_amd.assign import msa_switch
+
+    M = (1 << 64) - 1
+
+    def mix(z):
+        z &= M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    for n, seed in ((1, 0xA55), (7, 0xA55), (30, (1 << 63) + 12345)):
+        s = msa_switch(3000, n, seed)
+        want = [1 if mix(seed ^ (i << 8) ^ n) % (n + 1) == 0 else 0 for i in range(3000)]
+        assert s.tolist() == want
+
+
+def test_edge_travel_times_from_statistics():
+    """Routing costs and per-bin times from the statistics (library host
+    code) against their definitions."""
+    from paper_2406_08496_amd.assign import _p
+    from paper_2406_08496_amd.lpsim import load_library
+
+    lib = load_library()
+    rng = np.random.default_rng(2)
+    E, B = 500, 12
+    n = rng.integers(0, 5, E).astype(np.int32)
+    tts = (n * rng.integers(0, 90, E)).astype(np.int64)
+    free = rng.uniform(0.2, 40.0, E)
+    out = np.empty(E)
+    assert lib.lpsim_edge_tt(E, _p(tts), _p(n), _p(free), ctypes.c_double(0.5), _p(out)) == 0
+    mean = np.where(n > 0, tts / np.maximum(n, 1), free)
+    assert np.array_equal(out, np.maximum(mean, 1.0) * 0.5)
+    ex = rng.integers(0, 4, (E, B)).astype(np.int32)
+    ttb = (ex * rng.integers(1, 70, (E, B))).astype(np.int64)
+    outb = np.empty((E, B), np.float32)
+    assert lib.lpsim_edge_tt_bins(E, B, _p(ttb), _p(ex), _p(free), _p(outb)) == 0
+    want = np.where(ex > 0, ttb / np.maximum(ex, 1), free[:, None]).astype(np.float32)
+    assert np.array_equal(outb, want)
