@@ -393,9 +393,11 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
  * fixed point dist[x] = min over out-edges e = (x -> y) of dist[y] + cost[e]
  * in float64, the same lowest-edge-id rule among equally short choices, so
  * the same routes.  Label-correcting relaxation over (destination, node)
- * pairs with 64-bit atomic minima, then one pass that picks each node's tree
- * edge.  `stream` is a hipStream_t or NULL; the call returns when the trees
- * are on the host.  Device memory for the graph is kept until
+ * pairs with 64-bit atomic minima and a near-far split of the frontier, then
+ * one pass that picks each node's tree edge.  The trees stay on the device:
+ * lpsim_router_fill after this call walks them there and copies the routes
+ * back.  `stream` is a hipStream_t or NULL; the call returns when the solve
+ * is done.  Device memory for the graph and the trees is kept until
  * lpsim_router_destroy.  Errors: as lpsim_router_solve, and EDEVICE. */
 int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
                                const int32_t *dest, void *stream);

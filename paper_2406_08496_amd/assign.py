@@ -62,7 +62,10 @@ class Router:
             self.lib.lpsim_router_destroy(self._h)
             self._h = None
 
-    def routes(self, cost, origin, dest, old=None, take_new=None):
+    def routes(self, cost, origin, dest, old=None, take_new=None, timings=None):
+        """Routes for the trips: (offsets, edges); `timings` (a dict) gets
+        the seconds of the tree solve and of writing the routes added."""
+        t0 = time.perf_counter()
         cost = np.ascontiguousarray(cost, np.float64)
         origin = np.ascontiguousarray(origin, np.int32)
         dest = np.ascontiguousarray(dest, np.int32)
@@ -76,6 +79,7 @@ class Router:
             rc = self.lib.lpsim_router_solve(self._h, _p(cost), n, _p(origin), _p(dest))
         if rc:
             raise LpsimError(rc, "router solve (bad cost, ids, or unreachable destination)")
+        t1 = time.perf_counter()
         off = np.empty(n + 1, np.int64)
         oo = oe = tk = None
         if take_new is not None:
@@ -89,6 +93,10 @@ class Router:
         rc = self.lib.lpsim_router_fill(self._h, _p(oo), _p(oe), _p(tk), _p(off), _p(edges))
         if rc:
             raise LpsimError(rc, "router fill")
+        if timings is not None:
+            t2 = time.perf_counter()
+            timings["route_solve"] = timings.get("route_solve", 0.0) + (t1 - t0)
+            timings["route_fill"] = timings.get("route_fill", 0.0) + (t2 - t1)
         return off, edges[:off[-1]]
 
 
@@ -161,7 +169,8 @@ class Assignment:
     def reroute(self, cost_s, off, edges, n):
         t0 = time.perf_counter()
         take = msa_switch(len(self.origin), n, self.seed)
-        new = self.router.routes(cost_s, self.origin, self.dest, old=(off, edges), take_new=take)
+        new = self.router.routes(cost_s, self.origin, self.dest, old=(off, edges), take_new=take,
+                                 timings=self.timings)
         self._add("route", time.perf_counter() - t0)
         return new
 

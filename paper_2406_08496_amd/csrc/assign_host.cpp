@@ -28,7 +28,9 @@ void gpu_router_free(GpuRouter *g);
 int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const int64_t *in_off_h,
                          const int32_t *in_edges_h, const int32_t *in_src_h, const int32_t *src_h,
                          const int32_t *dst_h, const double *cost_h, const int32_t *dests, int32_t nd,
-                         int32_t *next_edge, hipStream_t s);
+                         int64_t n_trips, const int32_t *origin_h, const int32_t *dest_idx_h, hipStream_t s);
+int32_t gpu_router_routes(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, const int64_t *new_off,
+                          int32_t *new_edges, hipStream_t s);
 }  // namespace lpsim_route
 
 struct lpsim_router {
@@ -42,12 +44,11 @@ struct lpsim_router {
     std::vector<int32_t> dests;      // distinct destination nodes
     std::vector<int32_t> dest_idx;   // per trip
     std::vector<int32_t> origin;     // per trip
-    // tree edge per [dest][node] of the last solve: a host vector for host
-    // solves, page-locked memory (the GPU copies into it) for GPU solves
-    std::vector<int32_t> nx_vec;
-    int32_t *nx_pinned = nullptr;
-    size_t nx_pinned_cap = 0;
-    int32_t *next_edge = nullptr;
+    // tree edge per [dest][node] of the last host solve (a GPU solve keeps
+    // its trees on the device and walks them there)
+    std::vector<int32_t> next_edge;
+    bool on_gpu = false;         // the last solve ran on the GPU
+    void *gpu_stream = nullptr;  // and on this stream
     std::vector<int32_t> len;        // per trip, new route length (trips taking one)
     bool solved = false;
     lpsim_route::GpuRouter *gpu = nullptr;  // device copy of the graph (GPU solves)
@@ -148,7 +149,6 @@ int32_t lpsim_router_create(int32_t n_nodes, int32_t n_edges, const int32_t *src
 void lpsim_router_destroy(lpsim_router *r) {
     if (!r) return;
     lpsim_route::gpu_router_free(r->gpu);
-    if (r->nx_pinned) (void)hipHostFree(r->nx_pinned);
     delete r;
 }
 
@@ -177,32 +177,22 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
             r->dest_idx[(size_t)i] = idx[(size_t)t];
         }
         const int32_t nd = (int32_t)r->dests.size();
-        // every entry is written by the solve (-1 where there is no tree edge)
-        const size_t nx_n = (size_t)nd * r->n_nodes;
+        r->on_gpu = on_gpu;
+        r->gpu_stream = stream;
         if (on_gpu) {
-            if (r->nx_pinned_cap < nx_n) {
-                if (r->nx_pinned) (void)hipHostFree(r->nx_pinned);
-                r->nx_pinned = nullptr;
-                r->nx_pinned_cap = 0;
-                if (hipHostMalloc((void **)&r->nx_pinned, std::max<size_t>(nx_n, 1) * 4, hipHostMallocDefault) !=
-                    hipSuccess) {
-                    (void)hipGetLastError();
-                    r->nx_pinned = nullptr;
-                    return LPSIM_ENOMEM;
-                }
-                r->nx_pinned_cap = nx_n;
-            }
-            r->next_edge = r->nx_pinned;
-        } else {
-            if (r->nx_vec.size() < nx_n) r->nx_vec.resize(nx_n);
-            r->next_edge = r->nx_vec.data();
-        }
-        if (on_gpu) {
+            // the trees stay on the device, which also checks that every
+            // trip's destination can be reached
             const int32_t rc = lpsim_route::gpu_router_solve(
                 &r->gpu, r->n_nodes, r->n_edges, r->in_off.data(), r->in_edges.data(), r->in_src.data(),
-                r->src.data(), r->dst.data(), cost, r->dests.data(), nd, r->next_edge, (hipStream_t)stream);
+                r->src.data(), r->dst.data(), cost, r->dests.data(), nd, n_trips, r->origin.data(),
+                r->dest_idx.data(), (hipStream_t)stream);
             if (rc) return rc;
+            r->len.assign((size_t)n_trips, 0);
+            r->solved = true;
+            return LPSIM_OK;
         }
+        // every entry is written by the solve (-1 where there is no tree edge)
+        r->next_edge.resize((size_t)nd * r->n_nodes);
         r->in_cost.resize(r->in_edges.size());
         for (size_t j = 0; j < r->in_edges.size(); ++j) r->in_cost[j] = cost[r->in_edges[j]];
         const int32_t nw = std::max(1, std::min(r->n_threads, nd));
@@ -214,11 +204,11 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
             for (;;) {
                 const int32_t d = next.fetch_add(1);
                 if (d >= nd) break;
-                tree_to(*r, cost, r->dests[(size_t)d], r->next_edge + (size_t)d * r->n_nodes, dist[w],
+                tree_to(*r, cost, r->dests[(size_t)d], r->next_edge.data() + (size_t)d * r->n_nodes, dist[w],
                         done[w], heap[w]);
             }
         };
-        if (!on_gpu) {
+        {
             std::vector<std::thread> pool;
             for (int32_t w = 1; w < nw; ++w) pool.emplace_back(worker, w);
             worker(0);
@@ -292,6 +282,37 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
     if (take_new && (!old_off || !old_edges)) return LPSIM_EINVAL;
     const int64_t chunk = 65536;
     const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
+    if (r->on_gpu) {
+        // lengths of the new routes from walks on the device (every call, as
+        // below); with out_edges, the new routes come back packed and the
+        // old ones are copied on the host
+        const int32_t rc = lpsim_route::gpu_router_routes(r->gpu, take_new, r->len.data(), nullptr, nullptr,
+                                                          (hipStream_t)r->gpu_stream);
+        if (rc) return rc;
+        out_off[0] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const bool nw = !take_new || take_new[i];
+            out_off[i + 1] = out_off[i] + (nw ? r->len[(size_t)i] : old_off[i + 1] - old_off[i]);
+        }
+        if (!out_edges) return LPSIM_OK;
+        std::vector<int64_t> poff((size_t)n + 1);
+        poff[0] = 0;
+        for (int64_t i = 0; i < n; ++i) poff[(size_t)i + 1] = poff[(size_t)i] + r->len[(size_t)i];
+        std::vector<int32_t> packed((size_t)std::max<int64_t>(poff[(size_t)n], 1));
+        const int32_t rc2 = lpsim_route::gpu_router_routes(r->gpu, take_new, r->len.data(), poff.data(),
+                                                           packed.data(), (hipStream_t)r->gpu_stream);
+        if (rc2) return rc2;
+        parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
+            for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
+                int32_t *o = out_edges + out_off[i];
+                if (take_new && !take_new[i])
+                    std::memcpy(o, old_edges + old_off[i], (size_t)(old_off[i + 1] - old_off[i]) * 4);
+                else
+                    std::memcpy(o, packed.data() + poff[(size_t)i], (size_t)r->len[(size_t)i] * 4);
+            }
+        });
+        return LPSIM_OK;
+    }
     {
         // lengths of the new routes (walks down the destination's tree);
         // measured on every call, so a call that writes the edges without a
@@ -299,7 +320,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
         parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
             for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
                 if (take_new && !take_new[i]) continue;
-                const int32_t *nx = r->next_edge + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+                const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
                 const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
                 int32_t u = r->origin[(size_t)i], l = 0;
                 while (u != t && l <= r->n_nodes) {
@@ -324,7 +345,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
                 std::memcpy(o, old_edges + old_off[i], (size_t)(old_off[i + 1] - old_off[i]) * 4);
                 continue;
             }
-            const int32_t *nx = r->next_edge + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
+            const int32_t *nx = r->next_edge.data() + (size_t)r->dest_idx[(size_t)i] * r->n_nodes;
             const int32_t t = r->dests[(size_t)r->dest_idx[(size_t)i]];
             int32_t u = r->origin[(size_t)i];
             while (u != t) {

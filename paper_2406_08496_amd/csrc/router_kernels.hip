@@ -53,7 +53,20 @@ struct GpuRouter {
     uint32_t *flags[2] = {nullptr, nullptr};  // one bit per pair
     uint32_t *count = nullptr;                // [3] frontier sizes, by round mod 3
     int32_t *targets = nullptr;
+    // tree edge of every (destination, node) of the last solve
     int32_t *nx = nullptr;
+    size_t nx_cap = 0;
+    // trips of the last solve: origin node, destination index; destination
+    // nodes; downstream node of each edge (for walking the trees)
+    int32_t *trip_origin = nullptr, *trip_dest = nullptr, *dest_node = nullptr, *edge_dst = nullptr;
+    size_t trip_cap = 0, dest_cap = 0;
+    int64_t n_trips = 0;
+    uint8_t *take = nullptr;       // [n_trips] trips that take their new route
+    int32_t *len = nullptr;        // [n_trips] new route lengths
+    int64_t *poff = nullptr;       // [n_trips + 1] offsets of the packed new routes
+    int32_t *packed = nullptr;     // the new routes, packed
+    size_t packed_cap = 0;
+    uint32_t *bad = nullptr;       // a trip whose destination cannot be reached
     // far pile: pairs whose distance dropped above the threshold
     uint2 *far[2] = {nullptr, nullptr};
     uint32_t *far_flags = nullptr;             // one bit per pair in the pile
@@ -234,8 +247,9 @@ __global__ __launch_bounds__(THREADS) void k_split(GpuRouter g, int32_t round, d
 // tree edge of every (destination, node): the lowest out-edge whose
 // candidate equals the node's distance (-1 at the destination or if the
 // destination cannot be reached)
-__global__ void k_ties(GpuRouter g, int32_t nd) {
+__global__ void k_ties(GpuRouter g, int32_t nd, int32_t d0) {
     const size_t total = (size_t)nd * g.n;
+    int32_t *nx = g.nx + (size_t)d0 * g.n;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
         const int32_t d = (int32_t)(i / g.n), x = (int32_t)(i - (size_t)d * g.n);
         int32_t best = -1;
@@ -250,7 +264,50 @@ __global__ void k_ties(GpuRouter g, int32_t nd) {
                 }
             }
         }
-        g.nx[i] = best;
+        nx[i] = best;
+    }
+}
+
+// every trip's origin has a tree edge toward its destination
+__global__ void k_reachable(GpuRouter g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n_trips;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (g.nx[(size_t)g.trip_dest[i] * g.n + g.trip_origin[i]] < 0) atomicOr(g.bad, 1u);
+}
+
+// length of each new route: the walk down the destination's tree
+__global__ void k_walk_len(GpuRouter g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n_trips;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t l = 0;
+        if (g.take == nullptr || g.take[i]) {
+            const int32_t d = g.trip_dest[i], t = g.dest_node[d];
+            const int32_t *nx = g.nx + (size_t)d * g.n;
+            int32_t u = g.trip_origin[i];
+            while (u != t && l <= g.n) {
+                u = g.edge_dst[nx[u]];
+                ++l;
+            }
+        }
+        g.len[i] = l;
+    }
+}
+
+// the new routes, packed at offsets poff
+__global__ void k_walk_write(GpuRouter g) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n_trips;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (g.take != nullptr && !g.take[i]) continue;
+        const int32_t d = g.trip_dest[i], t = g.dest_node[d];
+        const int32_t *nx = g.nx + (size_t)d * g.n;
+        int32_t *o = g.packed + g.poff[i];
+        int32_t *const end = g.packed + g.poff[i + 1];
+        int32_t u = g.trip_origin[i];
+        while (u != t && o < end) {
+            const int32_t e = nx[u];
+            *o++ = e;
+            u = g.edge_dst[e];
+        }
     }
 }
 
@@ -284,7 +341,7 @@ void gpu_router_free(GpuRouter *g) {
 int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const int64_t *in_off_h,
                          const int32_t *in_edges_h, const int32_t *in_src_h, const int32_t *src_h,
                          const int32_t *dst_h, const double *cost_h, const int32_t *dests, int32_t nd,
-                         int32_t *next_edge, hipStream_t s) {
+                         int64_t n_trips, const int32_t *origin_h, const int32_t *dest_idx_h, hipStream_t s) {
     if (!*gp) {
         GpuRouter *g = new (std::nothrow) GpuRouter();
         if (!g) return LPSIM_ENOMEM;
@@ -316,6 +373,9 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         RCHK(alloc(g, g->count, 3));
         RCHK(alloc(g, g->far_count, 2));
         RCHK(alloc(g, g->far_min, 1));
+        RCHK(alloc(g, g->bad, 1));
+        RCHK(alloc(g, g->edge_dst, (size_t)n_edges));
+        RCHK(hipMemcpy(g->edge_dst, dst_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
         RCHK(hipMemcpy(g->in_off, io.data(), io.size() * 4, hipMemcpyHostToDevice));
         RCHK(hipMemcpy(g->in_src, in_src_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
         RCHK(hipMemcpy(g->in_edge, in_edges_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
@@ -335,13 +395,33 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         RCHK(alloc(g, g->front[1], pairs));
         RCHK(alloc(g, g->flags[0], (pairs + 31) / 32));
         RCHK(alloc(g, g->flags[1], (pairs + 31) / 32));
-        RCHK(alloc(g, g->nx, pairs));
         RCHK(alloc(g, g->targets, (size_t)per));
         RCHK(alloc(g, g->far[0], pairs));
         RCHK(alloc(g, g->far[1], pairs));
         RCHK(alloc(g, g->far_flags, (pairs + 31) / 32));
         g->cap_pairs = pairs;
     }
+    // trees of all destinations, the trips and their destinations
+    if (g->nx_cap < (size_t)nd * n_nodes) {
+        RCHK(alloc(g, g->nx, (size_t)nd * n_nodes));
+        g->nx_cap = (size_t)nd * n_nodes;
+    }
+    if (g->trip_cap < (size_t)n_trips) {
+        RCHK(alloc(g, g->trip_origin, (size_t)n_trips));
+        RCHK(alloc(g, g->trip_dest, (size_t)n_trips));
+        RCHK(alloc(g, g->take, (size_t)n_trips));
+        RCHK(alloc(g, g->len, (size_t)n_trips));
+        RCHK(alloc(g, g->poff, (size_t)n_trips + 1));
+        g->trip_cap = (size_t)n_trips;
+    }
+    if (g->dest_cap < (size_t)nd) {
+        RCHK(alloc(g, g->dest_node, (size_t)nd));
+        g->dest_cap = (size_t)nd;
+    }
+    g->n_trips = n_trips;
+    RCHK(hipMemcpyAsync(g->trip_origin, origin_h, (size_t)n_trips * 4, hipMemcpyHostToDevice, s));
+    RCHK(hipMemcpyAsync(g->trip_dest, dest_idx_h, (size_t)n_trips * 4, hipMemcpyHostToDevice, s));
+    RCHK(hipMemcpyAsync(g->dest_node, dests, (size_t)nd * 4, hipMemcpyHostToDevice, s));
     // threshold step of the near-far split: a few mean edge costs
     double mean_cost = 0.0;
     for (int32_t e = 0; e < n_edges; ++e) mean_cost += cost_h[e];
@@ -394,11 +474,46 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
             }
             ++round;
         }
-        hipLaunchKernelGGL(k_ties, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
+        hipLaunchKernelGGL(k_ties, dim3(GRID), dim3(THREADS), 0, s, *g, nb, d0);
         RCHK(hipGetLastError());
-        RCHK(hipMemcpyAsync(next_edge + (size_t)d0 * n_nodes, g->nx, (size_t)nb * n_nodes * 4, hipMemcpyDeviceToHost,
-                            s));
     }
+    const uint32_t zero = 0;
+    uint32_t bad = 0;
+    RCHK(hipMemcpyAsync(g->bad, &zero, 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_reachable, dim3(GRID), dim3(THREADS), 0, s, *g);
+    RCHK(hipGetLastError());
+    RCHK(hipMemcpyAsync(&bad, g->bad, 4, hipMemcpyDeviceToHost, s));
+    RCHK(hipStreamSynchronize(s));
+    return bad ? LPSIM_EINVAL : LPSIM_OK;
+}
+
+// Routes of the last GPU solve: new_len (host, n_trips) receives the length
+// of each new route (0 where take[i] == 0; take NULL takes all).  With
+// new_edges (host) and new_off (host, n_trips + 1 offsets of the packed new
+// routes, from new_len) the new routes are written there, packed.
+int32_t gpu_router_routes(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, const int64_t *new_off,
+                          int32_t *new_edges, hipStream_t s) {
+    if (!g) return LPSIM_ESTATE;
+    const int64_t n = g->n_trips;
+    if (take_h) RCHK(hipMemcpyAsync(g->take, take_h, (size_t)n, hipMemcpyHostToDevice, s));
+    GpuRouter gv = *g;
+    if (!take_h) gv.take = nullptr;
+    if (!new_edges) {
+        hipLaunchKernelGGL(k_walk_len, dim3(GRID), dim3(THREADS), 0, s, gv);
+        RCHK(hipGetLastError());
+        RCHK(hipMemcpyAsync(new_len, g->len, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+        return status(hipStreamSynchronize(s));
+    }
+    const size_t total = (size_t)new_off[n];
+    if (g->packed_cap < total) {
+        RCHK(alloc(g, g->packed, total));
+        g->packed_cap = total;
+    }
+    gv.packed = g->packed;
+    RCHK(hipMemcpyAsync(g->poff, new_off, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_walk_write, dim3(GRID), dim3(THREADS), 0, s, gv);
+    RCHK(hipGetLastError());
+    if (total) RCHK(hipMemcpyAsync(new_edges, g->packed, total * 4, hipMemcpyDeviceToHost, s));
     return status(hipStreamSynchronize(s));
 }
 
