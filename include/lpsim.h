@@ -310,16 +310,29 @@ int32_t lpsim_restore_state(lpsim_ctx *ctx, const void *host_buf, size_t bytes);
  * hipStream_t or NULL (the null stream); calls only enqueue work.
  * bfloat16 values are passed as uint16_t bit patterns.
  * Layer l maps in_l -> out_l with (in, out) = (32,256), (256,256), (256,256),
- * (256,16).  "wt" layout = [out_l][in_l] (forward); "w" layout = [in_l][out_l]
- * (backward); biases [out_l] binary32.
+ * (256,16); biases [out_l] binary32, binary32 weights [out_l][in_l].
+ * Fragment order: the bfloat16 matrices that the matrix cores read from
+ * memory (the weight copies, the kept hidden activations, the backward's
+ * gradients) are stored in the order of the MFMA operand fragments.  For a
+ * matrix of R rows (the contracted index, R a multiple of 32) and C features
+ * (a multiple of 16), element (r, f) sits at
+ *   ((r / 32) * (C / 16) + f / 16) * 512 + (f % 16 + 16 * ((r % 32) / 8)) * 8 + r % 8,
+ * so that one operand fragment is one contiguous 1 KiB read.  "wt" copy of
+ * layer l: rows in_l, features out_l (read by the forward); "w" copy: rows
+ * out_l padded to a multiple of 32 with zeros, features in_l (read by the
+ * backward).
  * Errors: EINVAL (null pointer, negative size), EDEVICE (launch failure).
  * ------------------------------------------------------------------------ */
 
 /* Fixed shape of the perceptron (any pointer may be NULL). */
 int32_t lpsim_mlp_shape(int32_t *in_dim, int32_t *hidden, int32_t *out_dim);
 
-/* y[n][16] = MLP(x[n][32]).  h: NULL, or 3 pointers to [n][256] bfloat16
- * buffers that receive the hidden activations (needed by the backward). */
+/* y[n][16] = MLP(x[n][32]), x and y row-major; wt: the 4 "wt" copies.
+ * h: NULL, or 3 pointers to buffers that receive the hidden activations
+ * (needed by the backward) in fragment order with rows = the batch rows
+ * padded to P = 64 ceil(n / 64) and 256 features, i.e. P * 256 bfloat16
+ * each.  Rows n .. P-1 are written too and carry no meaning.  x and every
+ * h[l] must be 16-byte aligned (EINVAL otherwise). */
 int32_t lpsim_mlp_forward(const uint16_t *x, const uint16_t *const *wt, const float *const *bias, float *y,
                           uint16_t *const *h, int64_t n, void *stream);
 
@@ -329,38 +342,44 @@ int32_t lpsim_mlp_forward(const uint16_t *x, const uint16_t *const *wt, const fl
 int32_t lpsim_mlp_loss_grad(const float *y, const float *target, const uint8_t *mask, int64_t n,
                             float inv_count, uint16_t *dz_out, float *loss_sum, void *stream);
 
-/* Bytes of the `workspace` that lpsim_mlp_backward needs for n_split batch
- * slices (binary32 partial sums, reduced in a fixed order). */
-size_t lpsim_mlp_workspace_bytes(int32_t n_split);
+/* Bytes of the `workspace` that lpsim_mlp_backward needs for n rows in
+ * n_split batch slices: the data gradients and the input in fragment order,
+ * then the slices' binary32 partial sums.  0 for invalid arguments. */
+size_t lpsim_mlp_workspace_bytes(int64_t n, int32_t n_split);
 
 /* Backward pass of the binary32-accumulated perceptron for a batch of n rows:
- * x and h (3 pointers) as produced by the forward, dz_out[n][16] bfloat16
- * output gradient, w (4 pointers, "w" layout bfloat16).  Writes dwt (4
- * pointers, "wt" layout binary32) and db (4 pointers).  dz_scratch: 2*n*256
- * bfloat16.  Deterministic for fixed n_split. */
+ * x[n][32] and h (3 pointers) as produced by the forward, dz_out[n][16]
+ * bfloat16 output gradient (row-major), w (4 pointers, the "w" copies).
+ * Writes dwt (4 pointers, binary32 [out_l][in_l]) and db (4 pointers).  The weight gradients are summed over the rows of each of
+ * n_split (1..1024) batch slices, then over the slices in order:
+ * deterministic for fixed n_split.  x, dz_out, every h[l] and w[l], and
+ * workspace (lpsim_mlp_workspace_bytes(n, n_split) bytes, caller-owned) must
+ * be 16-byte aligned.  n = 0 writes zero gradients (kernels only, no
+ * memset).  Three kernel launches. */
 int32_t lpsim_mlp_backward(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
-                           const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
-                           float *workspace, int32_t n_split, int64_t n, void *stream);
+                           const uint16_t *const *w, float *const *dwt, float *const *db, void *workspace,
+                           int32_t n_split, int64_t n, void *stream);
 
 /* lpsim_mlp_backward without any allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc): the same kernels and the same results
- * for the same n_split, with the data-gradient buffers and the workspace
- * taken from a static device array of the library (24.1 MiB, held by each
- * GPU the library runs on until the process ends).  Arguments as
- * lpsim_mlp_backward without dz_scratch and workspace.  Limits: n <= 8192
- * rows, n_split <= 64, else LPSIM_ECAPACITY.  n = 0 writes zero gradients
- * with kernels (no memset).  All calls on one GPU share its array, so calls
- * that overlap on one GPU (different streams, or threads) race; calls in one
- * stream's order do not.  Errors: EINVAL, ECAPACITY, EDEVICE. */
+ * for the same n_split, with the workspace taken from a static device array
+ * of the library (30.3 MiB, held by each GPU the library runs on until the
+ * process ends).  Arguments as lpsim_mlp_backward without workspace.
+ * Limits: n <= 8192 rows, n_split <= 32, else LPSIM_ECAPACITY.  All calls on
+ * one GPU share its array, so calls that overlap on one GPU (different
+ * streams, or threads) race; calls in one stream's order do not.
+ * Errors: EINVAL, ECAPACITY, EDEVICE. */
 int32_t lpsim_mlp_backward_noalloc(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
                                    const uint16_t *const *w, float *const *dwt, float *const *db,
                                    int32_t n_split, int64_t n, void *stream);
 
-/* Adam step (Kingma & Ba) on one binary32 matrix [rows][cols] ("wt" layout;
- * a bias is rows = 1): m, v moment buffers, t = step count from 1.  Also
- * writes the bfloat16 copies wt_bf16 ([rows][cols]) and w_bf16 ([cols][rows]),
- * either may be NULL. */
+/* Adam step (Kingma & Ba) on one binary32 matrix [rows][cols] = [out][in]
+ * (a bias is rows = 1): m, v moment buffers, t = step count from 1.  Also
+ * writes the bfloat16 copies in fragment order: wt_bf16 (rows cols, features
+ * rows) and w_bf16 (rows `rows` padded to 32, features cols), either may be
+ * NULL; the padding entries of w_bf16 are never written (the caller zeroes
+ * them once). */
 int32_t lpsim_mlp_adam(float *w, uint16_t *wt_bf16, uint16_t *w_bf16, const float *grad, float *m, float *v,
                        int32_t rows, int32_t cols, float lr, float beta1, float beta2, float eps, int32_t t,
                        void *stream);

@@ -2,40 +2,54 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "lpsim.h"
 #include "mlp_dev.h"
 
 using namespace lpsim_mlp;
 
-static const int IN_OF[4] = {IN, HID, HID, HID};
-static const int OUT_OF[4] = {HID, HID, HID, OUT};
-
 static int32_t hip_status(hipError_t e) { return e == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE; }
 
-// the backward's launches, from the last layer to the first: weight-gradient
-// partials per batch slice, their reduction in slice order, then the data
-// gradient of the layer's input (ping-pong between the two halves of
-// dz_scratch)
-static int32_t run_backward(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
-                            const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
-                            float *workspace, int32_t n_split, int64_t n, hipStream_t s) {
-    const uint16_t *layer_in[4] = {x, h[0], h[1], h[2]};
-    uint16_t *scratch[2] = {dz_scratch, dz_scratch + (size_t)n * HID};
-    const uint16_t *dz = dz_out;
-    int which = 0;
-    for (int l = 3; l >= 0; --l) {
-        MlpBwdWeightArgs wa{dz, layer_in[l], workspace, n};
-        hipError_t e = launch_bwd_weight(l, wa, n_split, s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        e = launch_reduce(workspace, n_split, OUT_OF[l], IN_OF[l], dwt[l], db[l], s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        if (l == 0) break;
-        MlpBwdDataArgs da{dz, w[l], layer_in[l], scratch[which], n};
-        e = launch_bwd_data(l, da, s);
-        if (e != hipSuccess) return LPSIM_EDEVICE;
-        dz = scratch[which];
-        which ^= 1;
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// the backward's arguments, its workspace carved as mlp_dev.h lays it out
+static MlpBwdArgs bwd_args(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                           const uint16_t *const *w, float *const *dwt, float *const *db, void *workspace,
+                           int32_t n_split, int64_t n) {
+    MlpBwdArgs a{};
+    const int64_t rows = padded_rows(n);
+    uint16_t *act = static_cast<uint16_t *>(workspace);
+    a.x = x;
+    for (int l = 0; l < 3; ++l) a.hT[l] = h[l];
+    a.dz_out = dz_out;
+    for (int l = 0; l < 4; ++l) {
+        a.w[l] = w[l];
+        a.dwt[l] = dwt[l];
+        a.db[l] = db[l];
+    }
+    a.dzT[3] = act;
+    a.dzT[2] = act + (size_t)OUT * rows;
+    a.dzT[1] = act + (size_t)(OUT + HID) * rows;
+    a.dzT[0] = act + (size_t)(OUT + 2 * HID) * rows;
+    a.xT = act + (size_t)(OUT + 3 * HID) * rows;
+    a.part = reinterpret_cast<float *>(static_cast<unsigned char *>(workspace) + bwd_act_bytes(rows));
+    a.n = n;
+    a.rows = rows;
+    a.n_split = n_split;
+    return a;
+}
+
+// arguments shared by both backward entry points
+static int32_t check_bwd(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
+                         const uint16_t *const *w, float *const *dwt, float *const *db, int32_t n_split, int64_t n) {
+    if (n < 0 || n_split < 1 || !h || !w || !dwt || !db) return LPSIM_EINVAL;
+    for (int l = 0; l < 4; ++l)
+        if (!w[l] || !dwt[l] || !db[l] || !aligned16(w[l])) return LPSIM_EINVAL;
+    if (n > 0) {
+        if (!x || !dz_out || !aligned16(x) || !aligned16(dz_out)) return LPSIM_EINVAL;
+        for (int l = 0; l < 3; ++l)
+            if (!h[l] || !aligned16(h[l])) return LPSIM_EINVAL;
     }
     return LPSIM_OK;
 }
@@ -51,7 +65,7 @@ int32_t lpsim_mlp_shape(int32_t *in_dim, int32_t *hidden, int32_t *out_dim) {
 
 int32_t lpsim_mlp_forward(const uint16_t *x, const uint16_t *const *wt, const float *const *bias, float *y,
                           uint16_t *const *h, int64_t n, void *stream) {
-    if (n < 0 || !wt || !bias || (n > 0 && (!x || !y))) return LPSIM_EINVAL;
+    if (n < 0 || !wt || !bias || (n > 0 && (!x || !y || !aligned16(x)))) return LPSIM_EINVAL;
     MlpFwdArgs a{};
     a.x = x;
     for (int l = 0; l < 4; ++l) {
@@ -59,7 +73,10 @@ int32_t lpsim_mlp_forward(const uint16_t *x, const uint16_t *const *wt, const fl
         a.wt[l] = wt[l];
         a.b[l] = bias[l];
     }
-    for (int l = 0; l < 3; ++l) a.h[l] = h ? h[l] : nullptr;
+    for (int l = 0; l < 3; ++l) {
+        a.h[l] = h ? h[l] : nullptr;
+        if (h && n > 0 && (!h[l] || !aligned16(h[l]))) return LPSIM_EINVAL;
+    }
     a.y = y;
     a.n = n;
     return hip_status(launch_fwd(a, (hipStream_t)stream));
@@ -72,45 +89,30 @@ int32_t lpsim_mlp_loss_grad(const float *y, const float *target, const uint8_t *
     return hip_status(launch_mse(y, target, mask, n * OUT, inv_count, dz_out, loss_sum, (hipStream_t)stream));
 }
 
-size_t lpsim_mlp_workspace_bytes(int32_t n_split) {
-    if (n_split < 1) return 0;
-    return (size_t)n_split * ((size_t)HID * HID + HID) * sizeof(float);
+size_t lpsim_mlp_workspace_bytes(int64_t n, int32_t n_split) {
+    if (n < 0 || n_split < 1) return 0;
+    return bwd_workspace_bytes(n, n_split);
 }
 
 int32_t lpsim_mlp_backward(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
-                           const uint16_t *const *w, float *const *dwt, float *const *db, uint16_t *dz_scratch,
-                           float *workspace, int32_t n_split, int64_t n, void *stream) {
-    if (n < 0 || n_split < 1 || n_split > 1024 || !h || !w || !dwt || !db) return LPSIM_EINVAL;
-    for (int l = 0; l < 4; ++l)
-        if (!w[l] || !dwt[l] || !db[l]) return LPSIM_EINVAL;
-    if (n > 0 && (!x || !h[0] || !h[1] || !h[2] || !dz_out || !dz_scratch || !workspace)) return LPSIM_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    // with no rows every gradient is zero
-    if (n == 0) {
-        for (int l = 0; l < 4; ++l) {
-            if (hipMemsetAsync(dwt[l], 0, (size_t)OUT_OF[l] * IN_OF[l] * 4, s) != hipSuccess) return LPSIM_EDEVICE;
-            if (hipMemsetAsync(db[l], 0, (size_t)OUT_OF[l] * 4, s) != hipSuccess) return LPSIM_EDEVICE;
-        }
-        return LPSIM_OK;
-    }
-    return run_backward(x, h, dz_out, w, dwt, db, dz_scratch, workspace, n_split, n, s);
+                           const uint16_t *const *w, float *const *dwt, float *const *db, void *workspace,
+                           int32_t n_split, int64_t n, void *stream) {
+    int32_t rc = check_bwd(x, h, dz_out, w, dwt, db, n_split, n);
+    if (rc != LPSIM_OK) return rc;
+    if (n_split > 1024 || !workspace || !aligned16(workspace)) return LPSIM_EINVAL;
+    // with no rows the kernels write zero partials and zero gradients
+    return hip_status(launch_bwd(bwd_args(x, h, dz_out, w, dwt, db, workspace, n_split, n), (hipStream_t)stream));
 }
 
 int32_t lpsim_mlp_backward_noalloc(const uint16_t *x, const uint16_t *const *h, const uint16_t *dz_out,
                                    const uint16_t *const *w, float *const *dwt, float *const *db, int32_t n_split,
                                    int64_t n, void *stream) {
-    if (n < 0 || n_split < 1 || !h || !w || !dwt || !db) return LPSIM_EINVAL;
+    int32_t rc = check_bwd(x, h, dz_out, w, dwt, db, n_split, n);
+    if (rc != LPSIM_OK) return rc;
     if (n > NOALLOC_MAX_ROWS || n_split > NOALLOC_MAX_SPLIT) return LPSIM_ECAPACITY;
-    for (int l = 0; l < 4; ++l)
-        if (!w[l] || !dwt[l] || !db[l]) return LPSIM_EINVAL;
-    if (n > 0 && (!x || !h[0] || !h[1] || !h[2] || !dz_out)) return LPSIM_EINVAL;
     void *base = nullptr;
     if (noalloc_scratch(&base) != hipSuccess) return LPSIM_EDEVICE;
-    uint16_t *dz_scratch = static_cast<uint16_t *>(base);
-    float *workspace = reinterpret_cast<float *>(static_cast<unsigned char *>(base) + NOALLOC_DZ_BYTES);
-    // with no rows the kernels write zero partials and zero gradients (no
-    // memset nodes, so the call can be captured in a graph)
-    return run_backward(x, h, dz_out, w, dwt, db, dz_scratch, workspace, n_split, n, (hipStream_t)stream);
+    return hip_status(launch_bwd(bwd_args(x, h, dz_out, w, dwt, db, base, n_split, n), (hipStream_t)stream));
 }
 
 int32_t lpsim_mlp_adam(float *w, uint16_t *wt_bf16, uint16_t *w_bf16, const float *grad, float *m, float *v,

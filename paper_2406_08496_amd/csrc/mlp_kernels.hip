@@ -4,15 +4,18 @@
 // (v_mfma_f32_16x16x32_bf16); hidden activations are rounded to bfloat16
 // (round to nearest even) once, after bias and ReLU.
 //
-// Weight layouts: "wt" = [out][in] (rows contiguous along the input), used by
-// the forward pass; "w" = [in][out], used by the backward data pass.  The
-// optimizer keeps both bfloat16 copies in step with the binary32 master.
+// Weights: the binary32 master is [out][in].  The matrix cores read two
+// bfloat16 copies in fragment order (mlp_dev.h): "wt" with rows = in
+// (contracted by the forward) and features = out, "w" with rows = out
+// (contracted by the backward data pass, padded to 32 with zeros) and
+// features = in.  The optimizer keeps both copies in step with the master.
 //
 // MFMA 16x16x32 lane layout (64 lanes, l = lane): the A operand of lane l is
 // row l%16, columns 8*(l/16) .. +7; the B operand is column l%16, rows
 // 8*(l/16) .. +7; the result element i of lane l is row 4*(l/16)+i, column
-// l%16.  Every fragment is therefore one contiguous 16-byte load when the
-// contraction index is the fastest-varying one in memory.
+// l%16.  An operand read from a row-major tile in LDS is one 16-byte read per
+// lane; one read from global memory comes from a fragment-order array, 16
+// bytes per lane in lane order.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,6 +28,8 @@ namespace lpsim_mlp {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TMC_MAX = 64;  // largest row tile of the data-gradient chain
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     // round to nearest, ties to even (values here are finite)
@@ -40,8 +45,6 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t *p) {
     return __builtin_bit_cast(bf16x8, u);
 }
 
-__device__ __forceinline__ bf16x8 zero_frag() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
-
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
@@ -54,7 +57,7 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 template <int K>
 __device__ __forceinline__ void hidden_layer(const uint16_t *A, int lda, const uint16_t *__restrict__ wt,
                                              const float *__restrict__ bias, uint16_t *out, int ldo,
-                                             uint16_t *__restrict__ out_g, int64_t row0, int64_t n) {
+                                             uint16_t *__restrict__ out_g, int64_t row0) {
     constexpr int RB = TM / 16, CB = HID / 16 / 4;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r16 = l & 15, kq = (l >> 4) * 8;
@@ -65,13 +68,13 @@ __device__ __forceinline__ void hidden_layer(const uint16_t *A, int lda, const u
     // current step's products run
     bf16x8 b[CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) b[cb] = frag(wt + (size_t)((w * CB + cb) * 16 + r16) * K + kq);
+    for (int cb = 0; cb < CB; ++cb) b[cb] = frag(wt + fo_block<HID>(0, (w * CB + cb) * 16) + l * 8);
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 bn[CB];
         if (k0 + 32 < K) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) bn[cb] = frag(wt + (size_t)((w * CB + cb) * 16 + r16) * K + k0 + 32 + kq);
+            for (int cb = 0; cb < CB; ++cb) bn[cb] = frag(wt + fo_block<HID>(k0 / 32 + 1, (w * CB + cb) * 16) + l * 8);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -88,16 +91,26 @@ __device__ __forceinline__ void hidden_layer(const uint16_t *A, int lda, const u
         const int col = (w * CB + cb) * 16 + r16;
         const float bc = bias[col];
         for (int rb = 0; rb < RB; ++rb) {
+            uint32_t hv[4];
             for (int i = 0; i < 4; ++i) {
                 const int row = rb * 16 + (l >> 4) * 4 + i;
                 const float z = acc[rb][cb][i] + bc;
                 const uint16_t h = f2bf(z > 0.0f ? z : 0.0f);
                 out[row * ldo + col] = h;
-                if (out_g && row0 + row < n) out_g[(size_t)(row0 + row) * HID + col] = h;
+                hv[i] = h;
             }
+            // fragment-order copy for the backward: the lane's four rows are
+            // consecutive there (one 8-byte store); rows past n hold the
+            // activations of a zero input and are never used with a nonzero
+            // gradient
+            const int64_t r = row0 + rb * 16 + (l >> 4) * 4;
+            if (out_g) *reinterpret_cast<uint2 *>(out_g + fo<HID>(r, col)) = make_uint2(hv[0] | hv[1] << 16, hv[2] | hv[3] << 16);
         }
     }
 }
+
+static_assert(TM == PANEL, "a forward tile is one panel of the kept activations");
+static_assert(PANEL % TMC_MAX == 0, "a chain tile lies inside one panel");
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[TM * LDX];
@@ -112,11 +125,11 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
         *reinterpret_cast<uint4 *>(xs + r * LDX + q) = v;
     }
     __syncthreads();
-    hidden_layer<IN>(xs, LDX, a.wt[0], a.b[0], hs0, LDH, a.h[0], row0, a.n);
+    hidden_layer<IN>(xs, LDX, a.wt[0], a.b[0], hs0, LDH, a.h[0], row0);
     __syncthreads();
-    hidden_layer<HID>(hs0, LDH, a.wt[1], a.b[1], hs1, LDH, a.h[1], row0, a.n);
+    hidden_layer<HID>(hs0, LDH, a.wt[1], a.b[1], hs1, LDH, a.h[1], row0);
     __syncthreads();
-    hidden_layer<HID>(hs1, LDH, a.wt[2], a.b[2], hs0, LDH, a.h[2], row0, a.n);
+    hidden_layer<HID>(hs1, LDH, a.wt[2], a.b[2], hs0, LDH, a.h[2], row0);
     __syncthreads();
     // output layer: N = OUT = 16, one column block; wave w owns row blocks 2w, 2w+1
     {
@@ -126,7 +139,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
         f32x4 acc[RBW];
         for (int j = 0; j < RBW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < HID; k0 += 32) {
-            const bf16x8 b = frag(a.wt[3] + (size_t)r16 * HID + k0 + kq);
+            const bf16x8 b = frag(a.wt[3] + fo_block<OUT>(k0 / 32, 0) + l * 8);
             for (int j = 0; j < RBW; ++j) {
                 const int rb = w * RBW + j;
                 acc[j] = mfma(frag(hs0 + (rb * 16 + r16) * LDH + k0 + kq), b, acc[j]);
@@ -143,172 +156,266 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// backward, data part: dz_prev = bf16(relu'(h_prev) * (dz @ W)), where W is
-// [K][N] ("in x out") so that the contraction over N is contiguous.
-// NC = contraction width padded to a multiple of 32.
+// backward, in three launches:
+//  1. k_mlp_bwd_chain: per tile of TMC rows, the data gradients of layers
+//     3, 2 and 1 one after the other (a row's chain needs only its own row),
+//     written feature-major; also x and dz_out feature-major.
+//  2. k_mlp_bwd_wgrad: partial weight and bias gradients of all four layers,
+//     one partial per batch slice.  With both operands feature-major the
+//     contraction over rows is contiguous in memory, so every MFMA fragment
+//     is one 16-byte load.
+//  3. k_mlp_bwd_reduce: sum of the slice partials in slice order.
 
-// rows per tile of the data-gradient kernel: its accumulators take TMD / 4
-// f32x4 per wave, which sets its occupancy (32 rows: 5 waves per SIMD,
-// faster than 64 or 128 rows)
-constexpr int TMD = 32;
+constexpr int TMC = 32;     // rows per block of the data-gradient chain (a multiple of 16)
+static_assert(TMC % 16 == 0 && TMC <= TMC_MAX, "whole MFMA row blocks inside one panel");
+constexpr int LDZ0 = 40;    // LDS pitch of the dz_out tile (16 columns padded to 32)
 
-template <int N, int K>
-__global__ __launch_bounds__(256) void k_mlp_bwd_data(MlpBwdDataArgs a) {
-    constexpr int NC = (N + 31) / 32 * 32;
-    constexpr int LDZ = NC + 8;
-    constexpr int RB = TMD / 16, CB = K / 16 / 4;
-    __shared__ __attribute__((aligned(16))) uint16_t zs[TMD * LDZ];
-    const int64_t row0 = (int64_t)blockIdx.x * TMD;
-    for (int c = threadIdx.x; c < TMD * NC / 8; c += blockDim.x) {
-        const int r = c / (NC / 8), q = (c % (NC / 8)) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (row0 + r < a.n && q < N) v = *reinterpret_cast<const uint4 *>(a.dz + (size_t)(row0 + r) * N + q);
-        *reinterpret_cast<uint4 *>(zs + r * LDZ + q) = v;
-    }
-    __syncthreads();
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r16 = l & 15, kq = (l >> 4) * 8;
-    // the loops over the accumulator tiles are unrolled so that acc stays in
-    // registers (a rolled loop indexes it dynamically and puts it in scratch)
+__device__ __forceinline__ bool relu_live(uint32_t h) { return h != 0 && !(h & 0x8000u); }
+
+// data gradient of one layer on a TMC-row tile:
+//   dz_prev[r][c] = bf16(relu'(h[r][c]) * sum_j dz[r][j] W[j][c])
+// A (dz rows, contraction j contiguous) comes from LDS; W is the "w" copy
+// (fragment order, rows j = the layer's N outputs padded to 32, features c).
+// The result goes to LDS (next layer's A operand, if D) and to dz_prevT in
+// fragment order.  Wave wv owns output columns 64 wv .. 64 wv + 63.
+template <int N>
+__device__ __forceinline__ void chain_layer(const uint16_t *A, int lda, const uint16_t *__restrict__ w,
+                                            const uint16_t *__restrict__ hT, uint16_t *D,
+                                            uint16_t *__restrict__ dzT, int64_t row0) {
+    constexpr int NC = (N + 31) / 32 * 32, KS = NC / 32;
+    constexpr int RB = TMC / 16, CB = HID / 16 / 4;
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = l & 15, g = l >> 4, kq = g * 8;
+    // the wave's weight fragments and ReLU masks, all issued before the products
+    bf16x8 b[KS][CB];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            b[ks][cb] = frag(w + fo_block<HID>(ks, (wv * CB + cb) * 16) + l * 8);
+        }
+    uint2 hm[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int col = (wv * CB + cb) * 16 + r16;
+            hm[rb][cb] = *reinterpret_cast<const uint2 *>(hT + fo<HID>(row0 + rb * 16 + g * 4, col));
+        }
     f32x4 acc[RB][CB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < NC; k0 += 32) {
-        bf16x8 b[CB];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int col = (w * CB + cb) * 16 + r16;
-            b[cb] = (k0 + kq < N) ? frag(a.w + (size_t)col * N + k0 + kq) : zero_frag();
-        }
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const bf16x8 av = frag(zs + (rb * 16 + r16) * LDZ + k0 + kq);
+            const bf16x8 av = frag(A + (rb * 16 + r16) * lda + ks * 32 + kq);
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(av, b[cb], acc[rb][cb]);
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(av, b[ks][cb], acc[rb][cb]);
         }
-    }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-        const int col = (w * CB + cb) * 16 + r16;
+        const int col = (wv * CB + cb) * 16 + r16;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
+            const uint32_t hw[4] = {hm[rb][cb].x & 0xffffu, hm[rb][cb].x >> 16, hm[rb][cb].y & 0xffffu,
+                                    hm[rb][cb].y >> 16};
+            uint32_t u[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t row = row0 + rb * 16 + (l >> 4) * 4 + i;
-                if (row >= a.n) continue;
-                const uint16_t hp = a.h_prev[(size_t)row * K + col];
-                const bool live = hp != 0 && !(hp & 0x8000u);  // relu output > 0
-                a.dz_prev[(size_t)row * K + col] = f2bf(live ? acc[rb][cb][i] : 0.0f);
+                u[i] = f2bf(relu_live(hw[i]) ? acc[rb][cb][i] : 0.0f);
+                if (D) D[(rb * 16 + g * 4 + i) * LDH + col] = (uint16_t)u[i];
             }
+            *reinterpret_cast<uint2 *>(dzT + fo<HID>(row0 + rb * 16 + g * 4, col)) =
+                make_uint2(u[0] | u[1] << 16, u[2] | u[3] << 16);
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// rows per staging chunk of the weight-gradient kernel (a multiple of 32)
-constexpr int WG_ROWS = 32;
+// gather 8 consecutive rows of column c of an LDS tile into one vector
+__device__ __forceinline__ uint4 lds_column8(const uint16_t *t, int pitch, int r, int c) {
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (uint32_t)t[(r + 2 * j) * pitch + c] | (uint32_t)t[(r + 2 * j + 1) * pitch + c] << 16;
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
 
-// backward, weight part: partial dwt[n][k] = sum over a batch slice of
-// dz[m][n] * h[m][k], and partial db[n] = sum dz[m][n].  Chunks of WG_ROWS
-// rows are read with 16-byte loads and stored transposed in LDS, so both MFMA
-// operands are contiguous along m; the next chunk is loaded into registers
-// while the current one is multiplied.  Block tile: TN (n) x TK (k); its
-// 16 x 16 output blocks are dealt evenly to the four waves, and each output
-// element is summed by one MFMA chain in chunk order.
-
-template <int N, int K>
-__global__ __launch_bounds__(256) void k_mlp_bwd_weight(MlpBwdWeightArgs a) {
-    constexpr int TN = N < 64 ? N : 64, TK = K < 64 ? K : 64;
-    constexpr int MC = WG_ROWS, LT = MC + 8;
-    static_assert(MC % 32 == 0, "chunks of whole MFMA steps");
-    constexpr int NB = TN / 16, KB = TK / 16, PER_WAVE = NB * KB / 4;
-    static_assert(NB * KB % 4 == 0 && PER_WAVE <= 4, "tile must split over four waves");
-    constexpr int VP = MC * TN / 8, VQ = MC * TK / 8;  // 16-byte vectors per chunk
-    constexpr int NVP = (VP + 255) / 256, NVQ = (VQ + 255) / 256;
-    __shared__ __attribute__((aligned(16))) uint16_t pt[TN * LT];  // dz^T tile [n][m]
-    __shared__ __attribute__((aligned(16))) uint16_t qt[TK * LT];  // h^T tile [k][m]
-    constexpr int n_tiles_k = K / TK;
-    const int tile = blockIdx.x;
-    const int nt = tile / n_tiles_k, kt = tile % n_tiles_k;
-    const int n0 = nt * TN, k0 = kt * TK;
-    const int split = blockIdx.y, n_split = gridDim.y;
-    const int64_t per = ((a.n + n_split - 1) / n_split + 31) / 32 * 32;
-    const int64_t m_lo = per * split, m_hi = m_lo + per < a.n ? m_lo + per : a.n;
+__global__ __launch_bounds__(256) void k_mlp_bwd_chain(MlpBwdArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t zs[TMC * LDZ0];
+    __shared__ __attribute__((aligned(16))) uint16_t xs[TMC * LDX];
+    __shared__ __attribute__((aligned(16))) uint16_t d0[TMC * LDH];
+    __shared__ __attribute__((aligned(16))) uint16_t d1[TMC * LDH];
+    const int64_t row0 = (int64_t)blockIdx.x * TMC;
     const int t = threadIdx.x;
-    const int l = t & 63, w = t >> 6;
-    const int r16 = l & 15, mq = (l >> 4) * 8;
-    uint4 vp[NVP], vq[NVQ];
-    auto load = [&](int64_t m0) {
-#pragma unroll
-        for (int u = 0; u < NVP; ++u) {
-            const int v = t + 256 * u, m = v / (TN / 8), c = (v % (TN / 8)) * 8;
-            vp[u] = make_uint4(0, 0, 0, 0);
-            if (v < VP && m0 + m < m_hi) vp[u] = *reinterpret_cast<const uint4 *>(a.dz + (size_t)(m0 + m) * N + n0 + c);
+    // stage dz_out (columns 16..31 zero) and x; rows past n are zero
+    for (int u = t; u < 2 * TMC * 4; u += 256) {
+        const int v = u % (TMC * 4), r = v >> 2, q = (v & 3) * 8;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (u < TMC * 4) {
+            if (q < OUT && row0 + r < a.n) val = *reinterpret_cast<const uint4 *>(a.dz_out + (size_t)(row0 + r) * OUT + q);
+            *reinterpret_cast<uint4 *>(zs + r * LDZ0 + q) = val;
+        } else {
+            if (row0 + r < a.n) val = *reinterpret_cast<const uint4 *>(a.x + (size_t)(row0 + r) * IN + q);
+            *reinterpret_cast<uint4 *>(xs + r * LDX + q) = val;
         }
+    }
+    __syncthreads();
+    // fragment-order copies of dz_out and x for the weight gradients
+    constexpr int RG = TMC / 8;
+    for (int u = t; u < (OUT + IN) * RG; u += 256) {
+        if (u < OUT * RG) {
+            const int c = u / RG, r = (u % RG) * 8;
+            *reinterpret_cast<uint4 *>(a.dzT[3] + fo<OUT>(row0 + r, c)) = lds_column8(zs, LDZ0, r, c);
+        } else {
+            const int w = u - OUT * RG, c = w / RG, r = (w % RG) * 8;
+            *reinterpret_cast<uint4 *>(a.xT + fo<IN>(row0 + r, c)) = lds_column8(xs, LDX, r, c);
+        }
+    }
+    chain_layer<OUT>(zs, LDZ0, a.w[3], a.hT[2], d0, a.dzT[2], row0);
+    __syncthreads();
+    chain_layer<HID>(d0, LDH, a.w[2], a.hT[1], d1, a.dzT[1], row0);
+    __syncthreads();
+    chain_layer<HID>(d1, LDH, a.w[1], a.hT[0], nullptr, a.dzT[0], row0);
+}
+
+// partial gradient of layer L over one batch slice, output tile
+// [o0, o0 + TO) x [i0, i0 + TI) of dwt_L (and db_L when i0 = 0):
+//   dwt[o][i] = sum_r dz[r][o] in[r][i],  db[o] = sum_r dz[r][o]
+// dz and in are in fragment order, whose rows are the contracted index here.
+// Each of the block's four waves takes a quarter of the slice's rows and sums
+// them in one MFMA chain, the next 32-row step's fragments loading while the
+// current one multiplies; the bias sums are the same products with an operand
+// of ones.  The four wave sums are added in wave order through LDS.
+constexpr int WG_TILES = 4 + 16 + 16 + 4;  // output tiles per slice (layers 0..3)
+constexpr int WG_RED = 64 * 64;            // largest tile
+
+template <int L>
+__device__ __forceinline__ void wgrad_tile(const MlpBwdArgs &a, int o0, int i0, int s, float *red) {
+    constexpr int NI = L == 0 ? IN : HID, NO = L == 3 ? OUT : HID;
+    constexpr int TO = NO < 64 ? NO : 64, TI = NI < 64 ? NI : 64;
+    constexpr int OB = TO / 16, IB = TI / 16;
+    const uint16_t *__restrict__ A = a.dzT[L];
+    const uint16_t *__restrict__ B = L == 0 ? a.xT : a.hT[L - 1];
+    const int t = threadIdx.x, l = t & 63, wv = t >> 6;
+    const int r16 = l & 15, g = l >> 4;
+    // the wave's rows: [lo, hi), whole 32-row steps (rows is a multiple of 64)
+    const int64_t rows = a.rows, quarters = 4 * (int64_t)a.n_split;
+    const int64_t per = ((rows + quarters - 1) / quarters + 31) / 32 * 32;
+    const int64_t lo = ((int64_t)s * 4 + wv) * per;
+    const int64_t hi = lo + per < rows ? lo + per : rows;
+    const bool bias = i0 == 0;
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u));
+    f32x4 acc[OB][IB], accb[OB];
 #pragma unroll
-        for (int u = 0; u < NVQ; ++u) {
-            const int v = t + 256 * u, m = v / (TK / 8), c = (v % (TK / 8)) * 8;
-            vq[u] = make_uint4(0, 0, 0, 0);
-            if (v < VQ && m0 + m < m_hi) vq[u] = *reinterpret_cast<const uint4 *>(a.h + (size_t)(m0 + m) * K + k0 + c);
+    for (int ob = 0; ob < OB; ++ob) {
+        accb[ob] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) acc[ob][ib] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // fragments of features f .. f+15 over one 32-row step, one contiguous
+    // 1 KiB read each; two steps stay in flight while the products run.  Steps past hi
+    // (a prefetch at the end) reread step lo and are not multiplied.
+    auto load = [&](int64_t r0, uint4 *va, uint4 *vb) {
+        const int64_t st = (r0 < hi ? r0 : lo) / 32;
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) va[ob] = *reinterpret_cast<const uint4 *>(A + fo_block<NO>(st, o0 + ob * 16) + l * 8);
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib) vb[ib] = *reinterpret_cast<const uint4 *>(B + fo_block<NI>(st, i0 + ib * 16) + l * 8);
+    };
+    auto step = [&](const uint4 *va, const uint4 *vb) {
+#pragma unroll
+        for (int ob = 0; ob < OB; ++ob) {
+            const bf16x8 fa = __builtin_bit_cast(bf16x8, va[ob]);
+#pragma unroll
+            for (int ib = 0; ib < IB; ++ib) acc[ob][ib] = mfma(fa, __builtin_bit_cast(bf16x8, vb[ib]), acc[ob][ib]);
+            if (bias) accb[ob] = mfma(fa, ones, accb[ob]);
         }
     };
-    f32x4 acc[PER_WAVE];
-#pragma unroll
-    for (int j = 0; j < PER_WAVE; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbias = 0.f;
-    if (m_lo < m_hi) load(m_lo);
-    for (int64_t m0 = m_lo; m0 < m_hi; m0 += MC) {
-        __syncthreads();  // the previous chunk's fragments have been read
-#pragma unroll
-        for (int u = 0; u < NVP; ++u) {
-            const int v = t + 256 * u, m = v / (TN / 8), c = (v % (TN / 8)) * 8;
-            const uint32_t wv[4] = {vp[u].x, vp[u].y, vp[u].z, vp[u].w};
-            if (v < VP)
-                for (int j = 0; j < 8; ++j) pt[(c + j) * LT + m] = (uint16_t)(wv[j >> 1] >> (16 * (j & 1)));
-        }
-#pragma unroll
-        for (int u = 0; u < NVQ; ++u) {
-            const int v = t + 256 * u, m = v / (TK / 8), c = (v % (TK / 8)) * 8;
-            const uint32_t wv[4] = {vq[u].x, vq[u].y, vq[u].z, vq[u].w};
-            if (v < VQ)
-                for (int j = 0; j < 8; ++j) qt[(c + j) * LT + m] = (uint16_t)(wv[j >> 1] >> (16 * (j & 1)));
-        }
-        __syncthreads();
-        if (m0 + MC < m_hi) load(m0 + MC);
-        // 32-row MFMA steps in increasing m: each element's sum keeps the row order
-#pragma unroll
-        for (int ms = 0; ms < MC; ms += 32)
-#pragma unroll
-            for (int j = 0; j < PER_WAVE; ++j) {
-                const int b = w * PER_WAVE + j, nb = b / KB, kb = b % KB;
-                acc[j] = mfma(frag(pt + (nb * 16 + r16) * LT + ms + mq), frag(qt + (kb * 16 + r16) * LT + ms + mq),
-                              acc[j]);
-            }
-        if (kt == 0 && t < TN)
-            for (int m = 0; m < MC; ++m) dbias += bf2f(pt[t * LT + m]);
-    }
-    float *part = a.ws + (size_t)split * (N * K + N);
-#pragma unroll
-    for (int j = 0; j < PER_WAVE; ++j) {
-        const int b = w * PER_WAVE + j, nb = b / KB, kb = b % KB;
-        for (int i = 0; i < 4; ++i) {
-            const int nn = n0 + nb * 16 + (l >> 4) * 4 + i, kk = k0 + kb * 16 + r16;
-            part[(size_t)nn * K + kk] = acc[j][i];
+    if (lo < hi) {
+        uint4 a0[OB], b0[IB], a1[OB], b1[IB];
+        load(lo, a0, b0);
+        load(lo + 32, a1, b1);
+        for (int64_t r0 = lo; r0 < hi; r0 += 64) {
+            step(a0, b0);
+            load(r0 + 64, a0, b0);
+            if (r0 + 32 < hi) step(a1, b1);
+            load(r0 + 96, a1, b1);
         }
     }
-    if (kt == 0 && t < TN) part[N * K + n0 + t] = dbias;
+    // wave sums to LDS, then their sum in wave order into the slice's partial
+    float *mine = red + wv * (WG_RED + 64);
+#pragma unroll
+    for (int ob = 0; ob < OB; ++ob) {
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) mine[(ob * 16 + g * 4 + i) * TI + ib * 16 + r16] = acc[ob][ib][i];
+        if (bias && r16 == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) mine[WG_RED + ob * 16 + g * 4 + i] = accb[ob][i];
+    }
+    __syncthreads();
+    float *part = a.part + (size_t)s * PAR_COUNT + PAR_W[L];
+    for (int e = t; e < TO * TI; e += 256) {
+        const float v = ((red[e] + red[(WG_RED + 64) + e]) + red[2 * (WG_RED + 64) + e]) + red[3 * (WG_RED + 64) + e];
+        part[(size_t)(o0 + e / TI) * NI + i0 + e % TI] = v;
+    }
+    if (bias && t < TO) {
+        const int e = WG_RED + t;
+        const float v = ((red[e] + red[(WG_RED + 64) + e]) + red[2 * (WG_RED + 64) + e]) + red[3 * (WG_RED + 64) + e];
+        part[NO * NI + o0 + t] = v;
+    }
 }
 
-// deterministic sum of the split partials
-__global__ void k_mlp_reduce(const float *ws, int n_split, int n_elem, int stride, float *dwt, float *db, int nk) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_elem; i += gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int p = 0; p < n_split; ++p) s += ws[(size_t)p * stride + i];
-        if (i < nk) dwt[i] = s;
-        else db[i - nk] = s;
+// block b: slice b mod n_split (so that, with a multiple of 8 slices, a
+// slice's blocks share one XCD and its L2), tile b / n_split
+__global__ __launch_bounds__(256) void k_mlp_bwd_wgrad(MlpBwdArgs a) {
+    __shared__ float red[4 * (WG_RED + 64)];
+    const int s = blockIdx.x % a.n_split, tile = blockIdx.x / a.n_split;
+    if (tile < 4) {
+        wgrad_tile<0>(a, tile * 64, 0, s, red);
+    } else if (tile < 20) {
+        const int u = tile - 4;
+        wgrad_tile<1>(a, (u / 4) * 64, (u % 4) * 64, s, red);
+    } else if (tile < 36) {
+        const int u = tile - 20;
+        wgrad_tile<2>(a, (u / 4) * 64, (u % 4) * 64, s, red);
+    } else {
+        wgrad_tile<3>(a, 0, (tile - 36) * 64, s, red);
     }
+}
+
+// gradients = sum of the slice partials, in slice order; four consecutive
+// parameters per thread (layer segments are multiples of four long)
+__global__ __launch_bounds__(256) void k_mlp_bwd_reduce(MlpBwdArgs a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= PAR_COUNT / 4) return;
+    const float4 *p = reinterpret_cast<const float4 *>(a.part) + q;
+    float4 v = p[0];
+    for (int k = 1; k < a.n_split; ++k) {
+        const float4 u = p[(size_t)k * (PAR_COUNT / 4)];
+        v.x += u.x;
+        v.y += u.y;
+        v.z += u.z;
+        v.w += u.w;
+    }
+    const int e = 4 * q;
+    const int L = e >= PAR_W[3] ? 3 : e >= PAR_W[2] ? 2 : e >= PAR_W[1] ? 1 : 0;
+    const int nw = (L == 3 ? OUT : HID) * (L == 0 ? IN : HID);
+    const int off = e - (L == 3 ? PAR_W[3] : L == 2 ? PAR_W[2] : L == 1 ? PAR_W[1] : 0);
+    float *dst;
+    switch (L) {
+        case 0: dst = off < nw ? a.dwt[0] + off : a.db[0] + (off - nw); break;
+        case 1: dst = off < nw ? a.dwt[1] + off : a.db[1] + (off - nw); break;
+        case 2: dst = off < nw ? a.dwt[2] + off : a.db[2] + (off - nw); break;
+        default: dst = off < nw ? a.dwt[3] + off : a.db[3] + (off - nw); break;
+    }
+    dst[0] = v.x;
+    dst[1] = v.y;
+    dst[2] = v.z;
+    dst[3] = v.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -333,8 +440,14 @@ __global__ void k_mlp_mse(const float *y, const float *t, const uint8_t *mask, i
 }
 
 // ---------------------------------------------------------------------------
-// Adam on one weight matrix of shape [rows][cols] ("wt" layout), bias vectors
-// with rows = 1.  Updates the binary32 master and both bfloat16 copies.
+// Adam on one weight matrix of shape [rows][cols] = [out][in] (a bias:
+// rows = 1).  Updates the binary32 master and both bfloat16 copies in
+// fragment order: wt (rows in, features out) and w (rows out, features in).
+
+__device__ __forceinline__ size_t fo_rt(int r, int f, int c) {
+    return ((size_t)(r >> 5) * (c >> 4) + (size_t)(f >> 4)) * 512 + (size_t)(((f & 15) + 16 * ((r & 31) >> 3)) * 8) +
+           (size_t)(r & 7);
+}
 
 __global__ void k_mlp_adam(float *w, uint16_t *wt_bf, uint16_t *w_bf, const float *g, float *m, float *v,
                            int rows, int cols, float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -349,11 +462,9 @@ __global__ void k_mlp_adam(float *w, uint16_t *wt_bf, uint16_t *w_bf, const floa
         const float wi = w[i] - lr * (mh / (sqrtf(vh) + eps));
         w[i] = wi;
         const uint16_t hb = f2bf(wi);
-        if (wt_bf) wt_bf[i] = hb;
-        if (w_bf) {
-            const int r = i / cols, c = i % cols;
-            w_bf[(size_t)c * rows + r] = hb;
-        }
+        const int o = i / cols, k = i % cols;
+        if (wt_bf) wt_bf[fo_rt(k, o, rows)] = hb;
+        if (w_bf) w_bf[fo_rt(o, k, cols)] = hb;
     }
 }
 
@@ -365,29 +476,11 @@ hipError_t launch_fwd(const MlpFwdArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_data(int layer, const MlpBwdDataArgs &a, hipStream_t s) {
-    const unsigned g = (unsigned)((a.n + TMD - 1) / TMD);
-    if (!g) return hipSuccess;
-    if (layer == 3) hipLaunchKernelGGL((k_mlp_bwd_data<OUT, HID>), dim3(g), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_mlp_bwd_data<HID, HID>), dim3(g), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_bwd_weight(int layer, const MlpBwdWeightArgs &a, int n_split, hipStream_t s) {
-    if (layer == 3) {
-        hipLaunchKernelGGL((k_mlp_bwd_weight<OUT, HID>), dim3((OUT / 16) * (HID / 64), n_split), dim3(256), 0, s, a);
-    } else if (layer == 0) {
-        hipLaunchKernelGGL((k_mlp_bwd_weight<HID, IN>), dim3((HID / 64) * (IN / 32), n_split), dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_mlp_bwd_weight<HID, HID>), dim3((HID / 64) * (HID / 64), n_split), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const float *ws, int n_split, int nn, int nk, float *dwt, float *db, hipStream_t s) {
-    const int n_elem = nn * nk + nn;
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((n_elem + 255) / 256), dim3(256), 0, s, ws, n_split, n_elem,
-                       nn * nk + nn, dwt, db, nn * nk);
+hipError_t launch_bwd(const MlpBwdArgs &a, hipStream_t s) {
+    const unsigned g1 = (unsigned)(a.rows / TMC);
+    if (g1) hipLaunchKernelGGL(k_mlp_bwd_chain, dim3(g1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_mlp_bwd_wgrad, dim3(WG_TILES * a.n_split), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3((PAR_COUNT / 4 + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

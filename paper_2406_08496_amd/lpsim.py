@@ -95,8 +95,8 @@ SIGNATURES = {
     "lpsim_mlp_shape": ([_vp, _vp, _vp], _i32),
     "lpsim_mlp_forward": ([_vp, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "lpsim_mlp_loss_grad": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp], _i32),
-    "lpsim_mlp_workspace_bytes": ([_i32], ctypes.c_size_t),
-    "lpsim_mlp_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
+    "lpsim_mlp_workspace_bytes": ([_i64, _i32], ctypes.c_size_t),
+    "lpsim_mlp_backward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
     "lpsim_mlp_backward_noalloc": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp], _i32),
     "lpsim_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, ctypes.c_float, ctypes.c_float,
                         ctypes.c_float, ctypes.c_float, _i32, _vp], _i32),

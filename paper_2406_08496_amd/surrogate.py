@@ -5,7 +5,10 @@ device memory and the stream); every arithmetic step -- forward, loss
 gradient, backward, Adam -- runs in the library's HIP kernels through the C
 ABI (`lpsim_mlp_*`).  bfloat16 tensors are passed by their bit patterns.
 
-Shape: x[32] -> 256 -> 256 -> 256 -> y[16]; layer l "wt" = [out_l][in_l].
+Shape: x[32] -> 256 -> 256 -> 256 -> y[16]; layer l's binary32 master weight
+is [out_l][in_l].  The matrix cores read bfloat16 matrices in fragment order
+(blocks of 32 rows x 16 features, `to_matrix` / `from_matrix` convert): the
+weight copies, the kept activations and the backward's gradients.
 """
 from __future__ import annotations
 
@@ -31,6 +34,25 @@ def _check(rc, what):
         raise LpsimError(rc, what)
 
 
+def to_matrix(t, rows, feats):
+    """A fragment-order array (rows a multiple of 32, feats of 16) -> the
+    [rows][feats] matrix.  Element (r, f) sits at
+    ((r//32) * (feats//16) + f//16) * 512 + (f%16 + 16 * ((r%32)//8)) * 8 + r%8."""
+    v = t.reshape(rows // 32, feats // 16, 4, 16, 8)  # step, feature block, row group, feature, row
+    return v.permute(0, 2, 4, 1, 3).reshape(rows, feats)
+
+
+def from_matrix(m):
+    """[rows][feats] matrix (rows a multiple of 32) -> fragment order (flat)."""
+    rows, feats = m.shape
+    v = m.reshape(rows // 32, 4, 8, feats // 16, 16)  # step, row group, row, feature block, feature
+    return v.permute(0, 3, 1, 4, 2).reshape(-1).contiguous()
+
+
+def _pad32(n):
+    return (n + 31) // 32 * 32
+
+
 def _stream():
     import torch
 
@@ -46,7 +68,7 @@ class EdgeMLP:
         self.torch = torch
         self.device = device
         # batch slices of the weight-gradient kernels: fixed if given, else
-        # one per 128 rows up to 128 (the result depends only on the count)
+        # chosen from the row count (the result depends only on the count)
         self.n_split = n_split
         if wt is None:
             rng = np.random.default_rng(seed)
@@ -66,12 +88,13 @@ class EdgeMLP:
         self._ws = None
 
     def _sync_bf16(self):
-        # bfloat16 copies of the binary32 master, written by the optimizer
-        # kernel with a zero step (w - 0 * update == w)
+        # bfloat16 copies of the binary32 master in fragment order, written by
+        # the optimizer kernel with a zero step (w - 0 * update == w): wt_bf
+        # with rows = in, features = out (forward), w_bf with rows = out
+        # (zero-padded to 32) and features = in (backward)
         torch = self.torch
-        self.wt_bf = [torch.empty(x.shape, dtype=torch.bfloat16, device=self.device) for x in self.w]
-        self.w_bf = [torch.empty((x.shape[1], x.shape[0]), dtype=torch.bfloat16, device=self.device)
-                     for x in self.w]
+        self.wt_bf = [torch.zeros(_pad32(i) * o, dtype=torch.bfloat16, device=self.device) for i, o in DIMS]
+        self.w_bf = [torch.zeros(_pad32(o) * i, dtype=torch.bfloat16, device=self.device) for i, o in DIMS]
         f = ctypes.c_float
         for l, (i, o) in enumerate(DIMS):
             m = torch.zeros_like(self.w[l])
@@ -81,14 +104,41 @@ class EdgeMLP:
                 ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(m.data_ptr()), o, i, f(0.0), f(0.9),
                 f(0.999), f(1e-8), 1, _stream()), "mlp bf16 copy")
 
+    # -- layout of the kept activations ---------------------------------------
+    # Fragment order over the rows padded to a multiple of 64.
+    @staticmethod
+    def padded_rows(n):
+        return (n + 63) // 64 * 64
+
+    @staticmethod
+    def hidden_rows(hs, n):
+        """The kept activations as [n][256] tensors."""
+        return [to_matrix(h, EdgeMLP.padded_rows(n), HID)[:n] for h in hs]
+
+    def pack_hidden(self, h):
+        """[n][256] activations -> the kept layout (padding rows zero), as the
+        backward takes them."""
+        n = h.shape[0]
+        full = self.torch.zeros((self.padded_rows(n), HID), dtype=h.dtype, device=h.device)
+        full[:n] = h
+        return from_matrix(full)
+
+    def weight_matrices(self, l):
+        """Layer l's bfloat16 copies as matrices: (wt_bf as [in][out], w_bf as
+        [out][in])."""
+        i, o = DIMS[l]
+        return to_matrix(self.wt_bf[l], _pad32(i), o)[:i], to_matrix(self.w_bf[l], _pad32(o), i)[:o]
+
     # -- inference ----------------------------------------------------------
     def forward(self, x, keep=False):
-        """x: [n][32] bfloat16 tensor -> y [n][16] float32 (and hidden if keep)."""
+        """x: [n][32] bfloat16 tensor -> y [n][16] float32; with keep, also the
+        hidden activations (fragment order, padded_rows(n) x 256 each)."""
         torch = self.torch
         assert x.dtype == torch.bfloat16 and x.shape[1] == IN and x.is_contiguous()
         n = x.shape[0]
         y = torch.empty((n, OUT), dtype=torch.float32, device=self.device)
-        hs = [torch.empty((n, HID), dtype=torch.bfloat16, device=self.device) for _ in range(3)] if keep else None
+        hs = [torch.empty(self.padded_rows(n) * HID, dtype=torch.bfloat16, device=self.device)
+              for _ in range(3)] if keep else None
         h_arr = _ptrs(hs) if keep else None
         _check(self.lib.lpsim_mlp_forward(ctypes.c_void_p(x.data_ptr()), _ptrs(self.wt_bf), _ptrs(self.b),
                                           ctypes.c_void_p(y.data_ptr()), h_arr, n, _stream()), "mlp forward")
@@ -114,20 +164,21 @@ class EdgeMLP:
         return loss, y
 
     def splits(self, n):
-        return self.n_split if self.n_split else max(1, min(128, (n + 127) // 128))
+        # 8 slices (one per XCD) up to 16k rows, then one per 2,048 rows up to 64
+        return self.n_split if self.n_split else max(8, min(64, n // 2048))
 
     def backward(self, x, hs, dz):
+        """hs: the forward's kept activations (fragment order)."""
         torch = self.torch
         n = x.shape[0]
         n_split = self.splits(n)
-        nbytes = self.lib.lpsim_mlp_workspace_bytes(n_split)
+        nbytes = self.lib.lpsim_mlp_workspace_bytes(n, n_split)
         if self._ws is None or self._ws.numel() * 4 < nbytes:
-            self._ws = torch.empty(nbytes // 4, dtype=torch.float32, device=self.device)
-        scratch = torch.empty((2, n, HID), dtype=torch.bfloat16, device=self.device)
+            self._ws = torch.empty((nbytes + 3) // 4, dtype=torch.float32, device=self.device)
         _check(self.lib.lpsim_mlp_backward(ctypes.c_void_p(x.data_ptr()), _ptrs(hs), ctypes.c_void_p(dz.data_ptr()),
                                            _ptrs(self.w_bf), _ptrs(self.g_w), _ptrs(self.g_b),
-                                           ctypes.c_void_p(scratch.data_ptr()), ctypes.c_void_p(self._ws.data_ptr()),
-                                           n_split, n, _stream()), "mlp backward")
+                                           ctypes.c_void_p(self._ws.data_ptr()), n_split, n, _stream()),
+               "mlp backward")
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1

@@ -60,8 +60,10 @@ def test_forward_integer_exact(torch, n):
     net = EdgeMLP(wt, b)
     y, hs = net.forward(bf(torch, x), keep=True)
     torch.cuda.synchronize()
+    rows = EdgeMLP.hidden_rows(hs, n)
     for l in range(3):
-        assert np.array_equal(to_np(hs[l]), hs_ref[l]), f"hidden layer {l + 1}"
+        assert hs[l].numel() == (n + 63) // 64 * 64 * 256
+        assert np.array_equal(to_np(rows[l].contiguous()), hs_ref[l]), f"hidden layer {l + 1}"
     assert np.array_equal(to_np(y), y_ref)
 
 
@@ -105,14 +107,16 @@ def test_backward_integer_exact(torch):
     for l in range(4):
         assert np.all(np.abs(dz).T @ np.abs(ins[l]) < 2 ** 24)
     net = EdgeMLP(wt, b, n_split=4)
-    net.backward(bf(torch, x), [bf(torch, h) for h in hs], bf(torch, dz))
+    net.backward(bf(torch, x), [net.pack_hidden(bf(torch, h)) for h in hs], bf(torch, dz))
     torch.cuda.synchronize()
     for l in range(4):
         assert np.array_equal(to_np(net.g_w[l]), dwt[l]), f"dW layer {l + 1}"
         assert np.array_equal(to_np(net.g_b[l]), db[l]), f"db layer {l + 1}"
 
 
-@pytest.mark.parametrize("n,n_split", [(4096, 8), (1000, 3)])
+# the training batch with its default slices, a row count that is not a
+# multiple of 8, and more slices than the rows fill
+@pytest.mark.parametrize("n,n_split", [(4096, 8), (1000, 3), (8192, None), (1001, 16), (77, 24)])
 def test_backward_realistic_within_bound(torch, n, n_split):
     case("mlp backward, realistic, n =", n, "splits", n_split)
     from paper_2406_08496_amd.surrogate import EdgeMLP
@@ -124,9 +128,9 @@ def test_backward_realistic_within_bound(torch, n, n_split):
     t = rng.normal(size=y.shape)
     dz, _ = mlp.loss_grad(y, t, None, 1.0 / y.size)
     dwt, db = mlp.backward(x, hs, dz, wt)
-    bw, bb = mlp.backward_bound(x, hs, dz, wt, n_split=n_split)
     net = EdgeMLP(wt, b, n_split=n_split)
-    net.backward(bf(torch, x), [bf(torch, h) for h in hs], bf(torch, dz))
+    bw, bb = mlp.backward_bound(x, hs, dz, wt, n_split=net.splits(n))
+    net.backward(bf(torch, x), [net.pack_hidden(bf(torch, h)) for h in hs], bf(torch, dz))
     torch.cuda.synchronize()
     for l in range(4):
         e = np.abs(to_np(net.g_w[l]) - dwt[l])
@@ -134,6 +138,39 @@ def test_backward_realistic_within_bound(torch, n, n_split):
         assert np.median(e) <= 1e-4 * np.median(np.abs(dwt[l])) + 1e-12
         eb = np.abs(to_np(net.g_b[l]) - db[l])
         assert np.all(eb <= bb[l] + 1e-30), f"db layer {l + 1}"
+
+
+def test_backward_through_forward_and_empty(torch):
+    """The backward on the forward's own kept activations (rows past n in
+    them hold the activations of a zero input) equals the backward on the
+    same rows repacked with zero padding; no rows gives zero gradients."""
+    case("mlp backward on kept activations, n = 1003, and n = 0")
+    from paper_2406_08496_amd.surrogate import EdgeMLP
+
+    wt, b = mlp.init_params(9)
+    rng = np.random.default_rng(10)
+    n = 1003
+    x = mlp.bf16(rng.normal(size=(n, 32)))
+    dz = mlp.bf16(rng.normal(size=(n, 16)) * 1e-3)
+    net = EdgeMLP(wt, b, n_split=5)
+    _, kept = net.forward(bf(torch, x), keep=True)
+    pad = EdgeMLP.hidden_rows(kept, EdgeMLP.padded_rows(n))[0][n:]
+    assert torch.count_nonzero(pad).item() > 0  # padding rows: relu(bias) of a zero input
+    net.backward(bf(torch, x), kept, bf(torch, dz))
+    got = [t.clone() for t in net.g_w + net.g_b]
+    repacked = [net.pack_hidden(r.contiguous()) for r in EdgeMLP.hidden_rows(kept, n)]
+    net.backward(bf(torch, x), repacked, bf(torch, dz))
+    torch.cuda.synchronize()
+    for u, v in zip(got, net.g_w + net.g_b):
+        assert torch.equal(u, v)
+    x0 = torch.zeros((0, 32), dtype=torch.bfloat16, device="cuda")
+    _, kept0 = net.forward(x0, keep=True)
+    for t in net.g_w + net.g_b:
+        t.fill_(float("nan"))
+    net.backward(x0, kept0, torch.zeros((0, 16), dtype=torch.bfloat16, device="cuda"))
+    torch.cuda.synchronize()
+    for t in net.g_w + net.g_b:
+        assert torch.count_nonzero(t).item() == 0
 
 
 def test_adam_matches_float64(torch):
@@ -158,8 +195,9 @@ def test_adam_matches_float64(torch):
     for l in range(4):
         w = to_np(net.w[l])
         assert np.allclose(w, w_ref[l], rtol=1e-5, atol=1e-6)
-        assert np.array_equal(to_np(net.wt_bf[l]), mlp.bf16(w))
-        assert np.array_equal(to_np(net.w_bf[l]), mlp.bf16(w).T)
+        wt_m, w_m = net.weight_matrices(l)
+        assert np.array_equal(to_np(wt_m.contiguous()), mlp.bf16(w).T)
+        assert np.array_equal(to_np(w_m.contiguous()), mlp.bf16(w))
 
 
 def test_training_lowers_loss(torch):

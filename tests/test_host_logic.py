@@ -85,7 +85,35 @@ def test_mlp_entry_points_validate_arguments():
     i, h, o = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert lib.lpsim_mlp_shape(ctypes.byref(i), ctypes.byref(h), ctypes.byref(o)) == 0
     assert (i.value, h.value, o.value) == (32, 256, 16)
-    assert lib.lpsim_mlp_workspace_bytes(8) > 0
+    # data gradients and input in fragment order (16 + 3*256 + 32 features,
+    # rows padded to 64, bfloat16), then the slice partials (144,144 binary32
+    # parameters each)
+    assert lib.lpsim_mlp_workspace_bytes(8192, 8) == 816 * 8192 * 2 + 8 * 144_144 * 4
+    assert lib.lpsim_mlp_workspace_bytes(1001, 3) == 816 * 1024 * 2 + 3 * 144_144 * 4
+    assert lib.lpsim_mlp_workspace_bytes(0, 1) == 144_144 * 4
+    assert lib.lpsim_mlp_workspace_bytes(10, 0) == 0
+    assert lib.lpsim_mlp_workspace_bytes(-1, 4) == 0
+    # argument checks run on the host, before any launch
+    assert lib.lpsim_mlp_backward(None, None, None, None, None, None, None, 1, 10, None) == -1
+    assert lib.lpsim_mlp_backward_noalloc(None, None, None, None, None, None, 1, 10, None) == -1
+
+
+def test_fragment_order_layout():
+    """to_matrix / from_matrix invert each other and place element (r, f) of
+    a [rows][feats] matrix where the MFMA 16x16x32 operand of lane
+    L = f%16 + 16*((r%32)//8) reads it: block (r//32, f//16), slot r%8."""
+    import torch
+
+    from paper_2406_08496_amd.surrogate import from_matrix, to_matrix
+
+    rows, feats = 64, 48
+    m = torch.arange(rows * feats, dtype=torch.int64).reshape(rows, feats)
+    flat = from_matrix(m)
+    for r, f in [(0, 0), (7, 15), (8, 0), (31, 47), (32, 16), (45, 33), (63, 47)]:
+        lane = f % 16 + 16 * ((r % 32) // 8)
+        off = ((r // 32) * (feats // 16) + f // 16) * 512 + lane * 8 + r % 8
+        assert flat[off].item() == m[r, f].item()
+    assert torch.equal(to_matrix(flat, rows, feats), m)
 
 
 def test_bench_mlp_flop_model():
