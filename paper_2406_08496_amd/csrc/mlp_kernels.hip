@@ -52,59 +52,77 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // ---------------------------------------------------------------------------
 // forward
 
-// hidden layer on a tile of TM rows: out = bf16(relu(A Wt^T + bias)), N = HID.
-// Wave w owns output column blocks 4w..4w+3 for all TM/16 row blocks.
-template <int K>
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two binary32 values rounded to bfloat16 (nearest even; one instruction on
+// gfx950), packed low-first
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// hidden layer on a tile of TM rows: out = bf16(relu(A W^T + bias)), N = HID,
+// computed transposed (out^T = W A^T: the weights are the MFMA's A operand,
+// the activation tile its B operand) so that each lane's four results are
+// four consecutive units of one row, written to LDS as one 8-byte store.
+// Wave w owns units 64 w .. 64 w + 63 for all TM/16 row blocks.  With
+// IN_PLACE the output overwrites the input tile once every wave has read it.
+template <int K, bool IN_PLACE>
 __device__ __forceinline__ void hidden_layer(const uint16_t *A, int lda, const uint16_t *__restrict__ wt,
                                              const float *__restrict__ bias, uint16_t *out, int ldo,
                                              uint16_t *__restrict__ out_g, int64_t row0) {
-    constexpr int RB = TM / 16, CB = HID / 16 / 4;
+    constexpr int RB = TM / 16, FB = HID / 16 / 4;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r16 = l & 15, kq = (l >> 4) * 8;
-    f32x4 acc[RB][CB];
-    for (int rb = 0; rb < RB; ++rb)
-        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int r16 = l & 15, g = l >> 4, kq = g * 8;
+    f32x4 acc[FB][RB];
+#pragma unroll
+    for (int fb = 0; fb < FB; ++fb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[fb][rb] = f32x4{0.f, 0.f, 0.f, 0.f};
     // weight fragments come from L2; the next k-step's are loaded while the
     // current step's products run
-    bf16x8 b[CB];
+    bf16x8 b[FB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) b[cb] = frag(wt + fo_block<HID>(0, (w * CB + cb) * 16) + l * 8);
+    for (int fb = 0; fb < FB; ++fb) b[fb] = frag(wt + fo_block<HID>(0, (w * FB + fb) * 16) + l * 8);
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 bn[CB];
+        bf16x8 bn[FB];
         if (k0 + 32 < K) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) bn[cb] = frag(wt + fo_block<HID>(k0 / 32 + 1, (w * CB + cb) * 16) + l * 8);
+            for (int fb = 0; fb < FB; ++fb) bn[fb] = frag(wt + fo_block<HID>(k0 / 32 + 1, (w * FB + fb) * 16) + l * 8);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const bf16x8 a = frag(A + (rb * 16 + r16) * lda + k0 + kq);
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a, b[cb], acc[rb][cb]);
+            for (int fb = 0; fb < FB; ++fb) acc[fb][rb] = mfma(b[fb], a, acc[fb][rb]);
         }
         if (k0 + 32 < K) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) b[cb] = bn[cb];
+            for (int fb = 0; fb < FB; ++fb) b[fb] = bn[fb];
         }
     }
-    for (int cb = 0; cb < CB; ++cb) {
-        const int col = (w * CB + cb) * 16 + r16;
-        const float bc = bias[col];
+    if (IN_PLACE) __syncthreads();
+#pragma unroll
+    for (int fb = 0; fb < FB; ++fb) {
+        const int f = (w * FB + fb) * 16 + g * 4;
+        const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
+#pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            uint32_t hv[4];
-            for (int i = 0; i < 4; ++i) {
-                const int row = rb * 16 + (l >> 4) * 4 + i;
-                const float z = acc[rb][cb][i] + bc;
-                const uint16_t h = f2bf(z > 0.0f ? z : 0.0f);
-                out[row * ldo + col] = h;
-                hv[i] = h;
-            }
-            // fragment-order copy for the backward: the lane's four rows are
-            // consecutive there (one 8-byte store); rows past n hold the
+            const int row = rb * 16 + r16;
+            const uint32_t p0 = pack_bf16(fmaxf(acc[fb][rb][0] + b0, 0.0f), fmaxf(acc[fb][rb][1] + b1, 0.0f));
+            const uint32_t p1 = pack_bf16(fmaxf(acc[fb][rb][2] + b2, 0.0f), fmaxf(acc[fb][rb][3] + b3, 0.0f));
+            *reinterpret_cast<uint2 *>(out + row * ldo + f) = make_uint2(p0, p1);
+            // fragment-order copy for the backward; rows past n hold the
             // activations of a zero input and are never used with a nonzero
             // gradient
-            const int64_t r = row0 + rb * 16 + (l >> 4) * 4;
-            if (out_g) *reinterpret_cast<uint2 *>(out_g + fo<HID>(r, col)) = make_uint2(hv[0] | hv[1] << 16, hv[2] | hv[3] << 16);
+            if (out_g) {
+                const int64_t r = row0 + row;
+                out_g[fo<HID>(r, f)] = (uint16_t)p0;
+                out_g[fo<HID>(r, f + 1)] = (uint16_t)(p0 >> 16);
+                out_g[fo<HID>(r, f + 2)] = (uint16_t)p1;
+                out_g[fo<HID>(r, f + 3)] = (uint16_t)(p1 >> 16);
+            }
         }
     }
 }
@@ -113,9 +131,10 @@ static_assert(TM == PANEL, "a forward tile is one panel of the kept activations"
 static_assert(PANEL % TMC_MAX == 0, "a chain tile lies inside one panel");
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
+    // one hidden tile, overwritten layer by layer (39 KiB of LDS per block,
+    // so that three blocks share a CU)
     __shared__ __attribute__((aligned(16))) uint16_t xs[TM * LDX];
     __shared__ __attribute__((aligned(16))) uint16_t hs0[TM * LDH];
-    __shared__ __attribute__((aligned(16))) uint16_t hs1[TM * LDH];
     const int64_t row0 = (int64_t)blockIdx.x * TM;
     // stage the input tile (rows past n are zero)
     for (int c = threadIdx.x; c < TM * IN / 8; c += blockDim.x) {
@@ -125,31 +144,38 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpFwdArgs a) {
         *reinterpret_cast<uint4 *>(xs + r * LDX + q) = v;
     }
     __syncthreads();
-    hidden_layer<IN>(xs, LDX, a.wt[0], a.b[0], hs0, LDH, a.h[0], row0);
+    hidden_layer<IN, false>(xs, LDX, a.wt[0], a.b[0], hs0, LDH, a.h[0], row0);
     __syncthreads();
-    hidden_layer<HID>(hs0, LDH, a.wt[1], a.b[1], hs1, LDH, a.h[1], row0);
+    hidden_layer<HID, true>(hs0, LDH, a.wt[1], a.b[1], hs0, LDH, a.h[1], row0);
     __syncthreads();
-    hidden_layer<HID>(hs1, LDH, a.wt[2], a.b[2], hs0, LDH, a.h[2], row0);
+    hidden_layer<HID, true>(hs0, LDH, a.wt[2], a.b[2], hs0, LDH, a.h[2], row0);
     __syncthreads();
-    // output layer: N = OUT = 16, one column block; wave w owns row blocks 2w, 2w+1
+    // output layer: N = OUT = 16, one unit block, transposed like the hidden
+    // layers; wave w owns the row blocks w RBW .. w RBW + RBW - 1
     {
         const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int r16 = l & 15, kq = (l >> 4) * 8;
+        const int r16 = l & 15, g = l >> 4, kq = g * 8;
         constexpr int RBW = TM / 16 / 4;
         f32x4 acc[RBW];
+#pragma unroll
         for (int j = 0; j < RBW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int k0 = 0; k0 < HID; k0 += 32) {
             const bf16x8 b = frag(a.wt[3] + fo_block<OUT>(k0 / 32, 0) + l * 8);
+#pragma unroll
             for (int j = 0; j < RBW; ++j) {
                 const int rb = w * RBW + j;
-                acc[j] = mfma(frag(hs0 + (rb * 16 + r16) * LDH + k0 + kq), b, acc[j]);
+                acc[j] = mfma(b, frag(hs0 + (rb * 16 + r16) * LDH + k0 + kq), acc[j]);
             }
         }
-        const float bc = a.b[3][r16];
+        const float *bo = a.b[3] + g * 4;
+#pragma unroll
         for (int j = 0; j < RBW; ++j) {
-            for (int i = 0; i < 4; ++i) {
-                const int row = (w * RBW + j) * 16 + (l >> 4) * 4 + i;
-                if (row0 + row < a.n) a.y[(size_t)(row0 + row) * OUT + r16] = acc[j][i] + bc;
+            const int64_t row = row0 + (w * RBW + j) * 16 + r16;
+            if (row < a.n) {
+                float *yr = a.y + (size_t)row * OUT + g * 4;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) yr[i] = acc[j][i] + bo[i];
             }
         }
     }
