@@ -59,11 +59,10 @@ struct Ctrl {
     uint32_t n_slots;      // slots in use in the live buffer (some may be dead)
     uint32_t n_new;        // departures appended this step (above n_slots)
     uint32_t n_comp;       // live slots counted by the reorder
-    uint32_t wq_cur;       // which waiting-queue buffer is live
-    uint32_t n_wq;         // due trips still waiting (live queue)
-    uint32_t n_wq_next;    // queue being built this step
+    uint32_t aq_cur;       // which list of origin lanes with waiting trips is live
+    uint32_t n_wq;         // due trips still waiting
     uint32_t dep_ev;       // a trip departed this step
-    uint32_t dep_done;     // departure-order positions already due
+    uint32_t dep_done;     // departure-order positions already queued (due by now)
 };
 
 struct Slots {
@@ -136,12 +135,32 @@ struct Dev {
     uint32_t n_trips;
     uint8_t *status;
     int32_t *arrival;
-    uint8_t *dclaim;      // [candidate position] the departure request was made this step
-    // due trips that have not entered yet, with their start record:
-    // {claim word of the start lane, its lane-map offset, first edge, trip id}
-    uint4 *wq[2];
-    const uint4 *orig;    // per trip: claim word, lane-map offset of the start
-                          // lane, first edge, route index of the first edge
+    // Due trips that have not entered yet, one set per origin lane (a lane
+    // some trip starts on).  Only the lowest trip id of a lane can win its
+    // entry (all of the lane's trips see the same entry window), so each
+    // step makes one request per origin lane with waiting trips.
+    //   ol_rec[o]   {claim word, lane-map offset, first edge, start of the
+    //               lane's segment in ol_trips} (n_ol + 1 records; the last
+    //               holds only the end of the final segment)
+    //   ol_trips    each lane's trips in increasing id, lane after lane
+    //   ol_bits     one bit per ol_trips entry: due and not yet entered
+    //   ol_head[o]  position in ol_trips of the lane's lowest waiting trip,
+    //               NO_NEXT when none waits
+    //   ol_cnt[o]   waiting trips of the lane
+    //   trip_ol[j]  {origin lane, position in ol_trips}
+    //   aq[2]       origin lanes with waiting trips: this step's list and the
+    //               next step's, counts in aq_n[2] (the move launch clears
+    //               the next one's count)
+    const uint4 *ol_rec;
+    const uint32_t *ol_trips;
+    uint32_t *ol_bits;
+    uint32_t *ol_head;
+    uint32_t *ol_cnt;
+    const uint2 *trip_ol;
+    uint32_t *aq[2];
+    uint32_t *aq_n;
+    uint32_t n_ol;
+    uint8_t *dclaim;      // [position in this step's lane list] the lane's request was made
     const uint4 *dep_rec; // per trip: route index of the first edge, route end,
                           // second edge (NO_NEXT if none), 0
     // per-edge counting sort of the slots (locality), every few steps
@@ -180,14 +199,18 @@ constexpr int PART_ROWS = MAX_BLOCKS + (int)MAX_HELPERS;
 void launch_set_next_blocked(const Dev &d, int32_t edge, bool on, hipStream_t s);
 // recompute the cached signal and blocked flags of every live vehicle
 void launch_refresh_flags(const Dev &d, hipStream_t s);
+// queue the trips at departure-order positions [lo, hi) into their origin
+// lanes; lanes that had no waiting trip join list aq[which]
+void launch_enqueue(const Dev &d, uint32_t lo, uint32_t hi, uint32_t which, hipStream_t s);
 // move (with departure requests in helper blocks)
 void launch_move(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 // resolve (with departures in helper blocks)
 void launch_resolve(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 // lane-change commit (if lane changes are on) and the end of the step, in
-// END_HELPERS leading blocks (the first does the work; 8 keeps the work
-// blocks' XCD placement)
+// END_HELPERS leading blocks (the first ends the step, the others queue the
+// trips that fall due at the next step; 8 keeps the work blocks' XCD
+// placement)
 constexpr uint32_t END_HELPERS = 8;
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s);

@@ -52,6 +52,7 @@ struct lpsim_ctx {
     int32_t n_edges = 0;
     uint64_t map_bytes = 0;
     uint32_t n_lane_slots = 0;
+    uint32_t due0 = 0;  // trips due at step 0 (departure-order positions)
     bool have_net = false;
 
     // trips
@@ -398,12 +399,21 @@ static int32_t reset_run_state(lpsim_ctx *c) {
     HIPCHK(c, hipMemset(d.partial, 0, (size_t)PART_ROWS * NPART * 8));
     HIPCHK(c, hipMemset(d.status, 0, N + 1));
     HIPCHK(c, hipMemset(d.arrival, 0xff, (N + 1) * 4));
-    HIPCHK(c, hipMemset(d.dclaim, 0, N + 1));
+    HIPCHK(c, hipMemset(d.dclaim, 0, (size_t)d.n_ol + 1));
+    HIPCHK(c, hipMemset(d.ol_bits, 0, (N / 32 + 1) * 4));
+    HIPCHK(c, hipMemset(d.ol_head, 0xff, ((size_t)d.n_ol + 1) * 4));
+    HIPCHK(c, hipMemset(d.ol_cnt, 0, ((size_t)d.n_ol + 1) * 4));
+    HIPCHK(c, hipMemset(d.aq_n, 0, 2 * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, E * 4));
     for (uint32_t *a : {d.rl_cnt, d.lcc_cnt, d.lc_cnt, d.blk_arr, d.blk_ev})
         HIPCHK(c, hipMemset(a, 0, (size_t)MAX_BLOCKS * 4));
+    // the trips due at step 0 wait in their origin lanes' sets
     Ctrl ct{};
+    ct.dep_done = c->due0;
+    ct.n_wq = c->due0;
     HIPCHK(c, hipMemcpy(d.ctrl, &ct, sizeof ct, hipMemcpyHostToDevice));
+    launch_enqueue(d, 0, c->due0, 0, nullptr);
+    HIPCHK(c, hipGetLastError());
     c->k = 0;
     // the blocked flags survive a reload of trips
     HIPCHK(c, hipMemcpy(d.aux, c->aux_h.data(), c->aux_h.size() * 4, hipMemcpyHostToDevice));
@@ -522,7 +532,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     std::vector<uint32_t> dep_hi((size_t)maxdep + 2, (uint32_t)N);  // one spare entry
     for (int32_t k = 0; k <= maxdep; ++k) dep_hi[(size_t)k] = cnt[(size_t)k + 1];
     // per-trip origin: claim word, lane-map offset of the start lane, first
-    // edge, route index of the first edge (start lane = scenario-local id mod lanes)
+    // edge (start lane = scenario-local id mod lanes)
     std::vector<uint4> orig((size_t)std::max<int64_t>(N, 1));
     // and what a departing trip's slot needs from its route: route index of
     // the first edge, route end, second edge (NO_NEXT if none)
@@ -539,11 +549,45 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
                     const uint4 R = rec_h[e0];
                     const uint32_t C = R.y & 0xffffu, nl = (R.y >> 16) & 0xffu;
                     const uint32_t l0 = (uint32_t)(t - t0) % nl;
-                    orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, r0);
+                    orig[(size_t)t] = make_uint4(R.w + l0, R.x + l0 * C, e0, 0u);
                     const uint32_t rend = roff[(size_t)t + 1];
                     dep_rec[(size_t)t] = make_uint4(r0, rend, r0 + 1 < rend ? route[r0 + 1] : NO_NEXT, 0u);
                 }
             });
+        }
+    }
+    // origin lanes (the lanes trips start on), numbered in claim-word order,
+    // each with its trips in increasing id
+    std::vector<uint32_t> ol_of((size_t)c->n_lane_slots + 1, 0);  // trips per claim word, then lane number
+    for (int64_t t = 0; t < N; ++t) ol_of[orig[(size_t)t].x]++;
+    std::vector<uint4> ol_rec;
+    uint32_t n_ol = 0;
+    {
+        uint32_t off = 0;
+        for (uint32_t w = 0; w < c->n_lane_slots; ++w) {
+            const uint32_t m = ol_of[w];
+            if (!m) {
+                ol_of[w] = NO_NEXT;
+                continue;
+            }
+            ol_of[w] = n_ol++;
+            ol_rec.push_back(make_uint4(w, 0u, 0u, off));
+            off += m;
+        }
+        ol_rec.push_back(make_uint4(0u, 0u, 0u, off));
+    }
+    std::vector<uint32_t> ol_trips((size_t)std::max<int64_t>(N, 1));
+    std::vector<uint2> trip_ol((size_t)std::max<int64_t>(N, 1));
+    {
+        std::vector<uint32_t> fill(n_ol, 0);
+        for (int64_t t = 0; t < N; ++t) {
+            const uint4 o = orig[(size_t)t];
+            const uint32_t l = ol_of[o.x];
+            ol_rec[l].y = o.y;
+            ol_rec[l].z = o.z;
+            const uint32_t pos = ol_rec[l].w + fill[l]++;
+            ol_trips[pos] = (uint32_t)t;
+            trip_ol[(size_t)t] = make_uint2(l, pos);
         }
     }
     std::vector<uint64_t> seeds(S);
@@ -567,9 +611,23 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if ((rc = upload(c, *(uint32_t **)&order_d, order.data(), order.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint32_t **)&dephi_d, dep_hi.data(), dep_hi.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint64_t **)&seeds_d, seeds.data(), seeds.size(), c->trip_allocs))) return rc;
-    const uint4 *orig_d;
-    if ((rc = upload(c, *(uint4 **)&orig_d, orig.data(), orig.size(), c->trip_allocs))) return rc;
-    d.orig = orig_d;
+    const uint4 *olrec_d;
+    if ((rc = upload(c, *(uint4 **)&olrec_d, ol_rec.data(), ol_rec.size(), c->trip_allocs))) return rc;
+    d.ol_rec = olrec_d;
+    const uint32_t *oltrips_d;
+    if ((rc = upload(c, *(uint32_t **)&oltrips_d, ol_trips.data(), ol_trips.size(), c->trip_allocs))) return rc;
+    d.ol_trips = oltrips_d;
+    const uint2 *tripol_d;
+    if ((rc = upload(c, *(uint2 **)&tripol_d, trip_ol.data(), trip_ol.size(), c->trip_allocs))) return rc;
+    d.trip_ol = tripol_d;
+    d.n_ol = n_ol;
+    if ((rc = alloc_n(c, d.ol_bits, (size_t)N / 32 + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.ol_head, (size_t)n_ol + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.ol_cnt, (size_t)n_ol + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.aq[0], (size_t)n_ol + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.aq[1], (size_t)n_ol + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.aq_n, (size_t)2, c->trip_allocs))) return rc;
+    c->due0 = N > 0 ? dep_hi[0] : 0u;
     const uint4 *deprec_d;
     if ((rc = upload(c, *(uint4 **)&deprec_d, dep_rec.data(), dep_rec.size(), c->trip_allocs))) return rc;
     d.dep_rec = deprec_d;
@@ -584,7 +642,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     d.scen_tbase = tbase_d;
     if ((rc = alloc_n(c, d.status, cap + 1, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.arrival, cap + 1, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.dclaim, cap + 1, c->trip_allocs))) return rc;
+    if ((rc = alloc_n(c, d.dclaim, (size_t)n_ol + 1, c->trip_allocs))) return rc;
     for (int b = 0; b < 2; ++b) {
         Slots &s = d.buf[b];
         if ((rc = alloc_n(c, s.x, cap, c->trip_allocs))) return rc;
@@ -613,8 +671,6 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     if ((rc = alloc_n(c, d.lc_cnt, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.blk_arr, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.blk_ev, (size_t)MAX_BLOCKS, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.wq[0], cap, c->trip_allocs))) return rc;
-    if ((rc = alloc_n(c, d.wq[1], cap, c->trip_allocs))) return rc;
     if ((rc = alloc_n(c, d.srank, cap, c->trip_allocs))) return rc;
     if ((rc = reset_run_state(c))) return rc;
     c->have_trips = true;
@@ -1245,16 +1301,24 @@ int32_t lpsim_kernel_times(lpsim_ctx *c, double *ms_out, int64_t *launches_out, 
 }
 
 // snapshot layout: header, ctrl, partial counters, lane map, trip status and
-// arrival, statistics, live slots
+// arrival, statistics, live slots, the waiting sets (bits, heads, counts)
+// and the live list of origin lanes with waiting trips
 struct SnapHeader {
     uint64_t magic;
-    uint64_t n_trips, n_edges, map_bytes, n_bins, n_slots, n_wq;
+    uint64_t n_trips, n_edges, map_bytes, n_bins, n_slots, n_aq;
 };
 
-static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_wq) {
+static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_aq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)PART_ROWS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
-           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (size_t)n_wq * 16;
+           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (N / 32 + 1) * 4 + ((size_t)c->d.n_ol + 1) * 8 +
+           (size_t)n_aq * 4;
+}
+
+// origin lanes in the live waiting list
+static int32_t read_n_aq(lpsim_ctx *c, const Ctrl &ct, uint32_t &n_aq) {
+    HIPCHK(c, hipMemcpy(&n_aq, c->d.aq_n + (ct.aq_cur & 1u), 4, hipMemcpyDeviceToHost));
+    return LPSIM_OK;
 }
 
 int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
@@ -1264,7 +1328,9 @@ int32_t lpsim_state_size(lpsim_ctx *c, size_t *bytes) {
     if ((rc = sync_all(c))) return rc;
     Ctrl ct;
     if ((rc = read_ctrl(c, ct))) return rc;
-    *bytes = snap_size(c, ct.n_slots, ct.n_wq);
+    uint32_t n_aq;
+    if ((rc = read_n_aq(c, ct, n_aq))) return rc;
+    *bytes = snap_size(c, ct.n_slots, n_aq);
     return LPSIM_OK;
 }
 
@@ -1275,11 +1341,13 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = sync_all(c))) return rc;
     Ctrl ct;
     if ((rc = read_ctrl(c, ct))) return rc;
-    if (bytes < snap_size(c, ct.n_slots, ct.n_wq)) return fail(c, LPSIM_EINVAL, "snapshot buffer too small");
+    uint32_t n_aq;
+    if ((rc = read_n_aq(c, ct, n_aq))) return rc;
+    if (bytes < snap_size(c, ct.n_slots, n_aq)) return fail(c, LPSIM_EINVAL, "snapshot buffer too small");
     const Dev &d = c->d;
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     char *p = (char *)buf;
-    SnapHeader h{SNAP_MAGIC, N, E, c->map_bytes, B, ct.n_slots, ct.n_wq};
+    SnapHeader h{SNAP_MAGIC, N, E, c->map_bytes, B, ct.n_slots, n_aq};
     std::memcpy(p, &h, sizeof h); p += sizeof h;
     std::memcpy(p, &ct, sizeof ct); p += sizeof ct;
     auto get = [&](const void *src, size_t n) -> int32_t {
@@ -1313,7 +1381,10 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = get(S.v0, n * 4))) return rc;
     if ((rc = get(S.tlb, n * 4))) return rc;
     if ((rc = get(S.tgt, n * 4))) return rc;
-    if ((rc = get(d.wq[ct.wq_cur], (size_t)ct.n_wq * 16))) return rc;
+    if ((rc = get(d.ol_bits, (N / 32 + 1) * 4))) return rc;
+    if ((rc = get(d.ol_head, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = get(d.ol_cnt, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = get(d.aq[ct.aq_cur & 1u], (size_t)n_aq * 4))) return rc;
     return LPSIM_OK;
 }
 
@@ -1328,12 +1399,12 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     const Dev &d = c->d;
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     if (h.magic != SNAP_MAGIC || h.n_trips != N || h.n_edges != E || h.map_bytes != c->map_bytes || h.n_bins != B ||
-        h.n_slots > c->slot_cap || h.n_wq > c->slot_cap || bytes < snap_size(c, h.n_slots, h.n_wq))
+        h.n_slots > c->slot_cap || h.n_aq > c->d.n_ol || bytes < snap_size(c, h.n_slots, h.n_aq))
         return fail(c, LPSIM_EINVAL, "snapshot does not match this instance");
     Ctrl ct;
     std::memcpy(&ct, p, sizeof ct); p += sizeof ct;
     ct.cur = 0;
-    ct.wq_cur = 0;
+    ct.aq_cur = 0;
     auto put = [&](void *dst, size_t n) -> int32_t {
         HIPCHK(c, hipMemcpy(dst, p, n, hipMemcpyHostToDevice));
         p += n;
@@ -1365,7 +1436,12 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(S.v0, n * 4))) return rc;
     if ((rc = put(S.tlb, n * 4))) return rc;
     if ((rc = put(S.tgt, n * 4))) return rc;
-    if ((rc = put(d.wq[0], (size_t)h.n_wq * 16))) return rc;
+    if ((rc = put(d.ol_bits, (N / 32 + 1) * 4))) return rc;
+    if ((rc = put(d.ol_head, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = put(d.ol_cnt, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = put(d.aq[0], (size_t)h.n_aq * 4))) return rc;
+    const uint32_t aq_n[2] = {(uint32_t)h.n_aq, 0u};
+    HIPCHK(c, hipMemcpy(d.aq_n, aq_n, sizeof aq_n, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, (size_t)c->n_edges * 4));
     HIPCHK(c, hipMemcpy(d.ctrl + (ct.k & 1), &ct, sizeof ct, hipMemcpyHostToDevice));

@@ -7,16 +7,18 @@
 //   move     reads the lane map of step k: leader scan, IDM / free move,
 //            stop line, crossing; entry requests of crossing vehicles and of
 //            due trips go into one 32-bit word per target lane by atomicMin
-//            of the trip id (exclusive entry, lowest id wins);
+//            of the trip id (exclusive entry, lowest id wins); due trips wait
+//            in per-origin-lane sets, and only each set's lowest id asks;
 //   resolve  winners enter, losers wait at the last cell, arrivals leave;
 //            each vehicle clears its old cell byte and writes its new one --
 //            no two vehicles touch the same byte in this kernel (a mover never
 //            lands on a cell another vehicle occupied at step k, entries need
 //            the first W cells free); per-edge statistics by atomics; trips
-//            that could not enter go to the next waiting queue;
+//            that could not enter keep waiting in their lane's set;
 //   lanechg  mandatory lane change decided on the post-move map;
-//   commit   writes the accepted lane changes into the map, then the last
-//            block to finish does the step's bookkeeping (clock, counts).
+//   commit   writes the accepted lane changes into the map; its helper
+//            blocks end the step (clock, counts) and queue the trips that
+//            fall due at the next step.
 //   reorder  (every few steps) a counting sort of the live vehicle slots by
 //            edge: drops finished vehicles and puts vehicles of one edge next
 //            to each other, so neighbouring lanes share cache lines.
@@ -340,17 +342,21 @@ __device__ __forceinline__ void counts_flush(const Dev &d, BlockCounts *s, uint3
     }
 }
 
-// the trip at position q of this step's departure candidates: the live
-// waiting queue first, then the trips that fall due at this step
-// {claim word, start-lane offset, first edge, trip id}; *fresh is set for a
-// trip that falls due now (its start record read from the trip table)
-__device__ __forceinline__ uint4 candidate(const Dev &d, const Ctrl *ctl, uint32_t q, bool *fresh) {
-    const uint32_t nwq = ctl->n_wq;
-    *fresh = q >= nwq;
-    if (q < nwq) return d.wq[ctl->wq_cur][q];
-    const uint32_t j = d.dep_order[ctl->dep_done + (q - nwq)];
-    const uint4 o = d.orig[j];
-    return make_uint4(o.x, o.y, o.z, j);
+// an origin lane's waiting set: the bits of ol_bits over its ol_trips
+// segment [beg, end) (neighbouring lanes may share a word).  First waiting
+// position after position p of the segment, or NO_NEXT.
+__device__ __forceinline__ uint32_t next_waiting(const Dev &d, uint32_t p, uint32_t end) {
+    const uint32_t q = p + 1;
+    if (q >= end) return NO_NEXT;
+    const uint32_t w_end = (end + 31) >> 5;
+    uint32_t w = q >> 5;
+    uint32_t bits = d.ol_bits[w] & (0xffffffffu << (q & 31));
+    while (bits == 0u) {
+        if (++w >= w_end) return NO_NEXT;
+        bits = d.ol_bits[w];
+    }
+    const uint32_t r = (w << 5) + (uint32_t)__builtin_ctz(bits);
+    return r < end ? r : NO_NEXT;
 }
 
 // exclusive scan of one value per thread over the block (blockDim.x a
@@ -522,29 +528,33 @@ __device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t
 // ---------------------------------------------------------------------------
 // departure candidates: due trips request their start lane (reads step k)
 
-__device__ __forceinline__ uint32_t n_candidates(const Dev &d, const Ctrl *ctl) {
-    return ctl->n_wq + (dep_hi_of(d, ctl->k) - ctl->dep_done);
-}
-
 // runs in the X leading blocks of the move launch (hb = 0..X-1), beside the
-// move: it reads the same step-k map and only adds claims.  Its bytes (queue
-// entry 16, or for a trip falling due its id 4 and start record 16; the
-// first edge's flags 4, the entry window W, the request flag 1) count into
-// row MAX_BLOCKS + hb.
+// move: it reads the same step-k map and only adds claims.  One request per
+// origin lane with waiting trips, for its lowest trip id: the lane's trips
+// share the entry window and the first edge, so no other of them can win.
+// Its bytes (list entry 4, lane record 16, head 4, trip id 4, the first
+// edge's flags 4, the entry window W, the request flag 1) count into row
+// MAX_BLOCKS + hb.
 __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X) {
     __shared__ BlockCounts cnt;
     counts_init(&cnt);
     const Ctrl *ctl = d.ctrl;
-    const uint32_t nc = n_candidates(d, ctl);
+    const uint32_t cur = ctl->aq_cur;
+    // the next step's lane list starts empty (last read by the previous step)
+    if (hb == 0 && threadIdx.x == 0) d.aq_n[cur ^ 1u] = 0u;
+    const uint32_t nc = d.aq_n[cur];
+    const uint32_t *aq = d.aq[cur];
     const uint32_t W = (uint32_t)d.p.W;
     uint32_t bytes = 0;
     for (uint32_t q = hb * blockDim.x + threadIdx.x; q < nc; q += X * blockDim.x) {
-        bool fresh;
-        const uint4 o = candidate(d, ctl, q, &fresh);
-        const bool ok = !(d.aux[o.z] & AUX_BLOCKED) && first_occ(d.map, o.y, 0, (int32_t)W - 1) < 0;
+        const uint32_t o = aq[q];
+        const uint4 R = d.ol_rec[o];
+        const uint32_t h = d.ol_head[o];  // a listed lane has a waiting trip
+        const uint32_t j = h != NO_NEXT ? d.ol_trips[h] : NO_NEXT;
+        const bool ok = h != NO_NEXT && !(d.aux[R.z] & AUX_BLOCKED) && first_occ(d.map, R.y, 0, (int32_t)W - 1) < 0;
         d.dclaim[q] = ok ? 1 : 0;
-        if (ok) atomicMin(&d.claims[o.x], o.w);
-        bytes += (fresh ? 4u + 16u : 16u) + 4u + W + 1u;
+        if (ok) atomicMin(&d.claims[R.x], j);
+        bytes += 4u + 16u + 4u + 4u + 4u + W + 1u;
     }
     if (bytes) atomicAdd(&cnt.c[P_SCAN], bytes);
     counts_flush(d, &cnt, MAX_BLOCKS + hb);
@@ -687,9 +697,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) vo
 }
 
 // ---------------------------------------------------------------------------
-// depart: candidates that won their start lane become vehicles, the others
-// wait in the next queue.  Both lists are built with block-wide scans, so a
-// block makes one atomic per list per pass of 4096 candidates.
+// depart: the lowest waiting trip of an origin lane that won its claim
+// becomes a vehicle and leaves the lane's set; lanes that still hold waiting
+// trips go to the next step's list.  Both lists are built with block-wide
+// scans, so a block makes one atomic per list per pass.
 
 // runs in the X leading blocks of the resolve launch (hb = 0..X-1); its
 // counters go to row MAX_BLOCKS + hb
@@ -700,42 +711,57 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
     counts_init(&cnt);
     Ctrl *ctl = d.ctrl;
     const int32_t k = ctl->k;
-    const uint32_t nc = n_candidates(d, ctl);
+    const uint32_t cur = ctl->aq_cur;
+    const uint32_t nc = d.aq_n[cur];
+    const uint32_t *aq = d.aq[cur];
+    uint32_t *aq_next = d.aq[cur ^ 1u];
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
-    uint4 *wq_next = ctl->wq_cur ? d.wq[0] : d.wq[1];
     bool any_dep = false;
     for (uint32_t pass0 = hb * blockDim.x; pass0 < nc; pass0 += X * blockDim.x) {
         const uint32_t q = pass0 + threadIdx.x;
         bool dep = false, rq = false;
-        uint4 o = make_uint4(0, 0, 0, 0);
+        uint32_t o = 0, j = 0;
+        uint4 R = make_uint4(0, 0, 0, 0);
         // a winner's edge records and route data, read before the block
-        // scans: with the claim word for candidates that made a request,
-        // then the second edge's record and aux word for winners
+        // scans: with the claim word for lanes that made a request, then the
+        // second edge's record and aux word for winners
         uint4 E0 = make_uint4(0, 0, 0, 0), dr = make_uint4(0, 0, NO_NEXT, 0), En0 = make_uint4(0, 0, 0, 0);
         uint32_t ax0 = 0, sg0 = 0;
         if (q < nc) {
-            bool fresh;
-            o = candidate(d, ctl, q, &fresh);
+            o = aq[q];
+            R = d.ol_rec[o];
+            const uint32_t h = d.ol_head[o];
+            uint32_t wc = d.ol_cnt[o];
             uint32_t claimed = d.dclaim[q];
-            uint32_t cw = d.claims[o.x];
+            j = h != NO_NEXT ? d.ol_trips[h] : NO_NEXT;
+            uint32_t cw = d.claims[R.x];
             if (claimed) {
-                E0 = d.edge[o.z];
-                dr = d.dep_rec[o.w];
-                if (d.sig != nullptr) sg0 = d.sig[o.z].x;
+                E0 = d.edge[R.z];
+                dr = d.dep_rec[j];
+                if (d.sig != nullptr) sg0 = d.sig[R.z].x;
             }
             ISSUED_TOGETHER4(claimed, cw, E0.x, dr.x);
-            if (cw == o.w) {
-                d.claims[o.x] = 0xffffffffu;
+            if (claimed && cw == j) {
+                d.claims[R.x] = 0xffffffffu;
                 dep = true;
                 if (dr.z != NO_NEXT) {
                     En0 = d.edge[dr.z];
                     ax0 = d.aux[dr.z];
                 }
+                // leave the set: clear the bit (a word may hold bits of a
+                // neighbouring lane), find the next waiting trip
+                atomicAnd(&d.ol_bits[h >> 5], ~(1u << (h & 31)));
+                wc -= 1u;
+                d.ol_cnt[o] = wc;
+                const uint32_t nh = wc ? next_waiting(d, h, d.ol_rec[o + 1].w) : NO_NEXT;
+                d.ol_head[o] = nh;
+                rq = nh != NO_NEXT;
             } else {
-                if (claimed) atomicAdd(&cnt.c[P_LOST], 1u);
-                rq = true;
+                rq = h != NO_NEXT;
             }
+            // every other trip of a lane that asked lost its request
+            if (claimed && wc) atomicAdd(&cnt.c[P_LOST], wc);
         }
         uint32_t tot_dep, tot_rq;
         const uint32_t my_dep = block_scan(dep ? 1u : 0u, wsum, tot_dep);
@@ -743,16 +769,15 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
         const uint32_t my_rq = block_scan(rq ? 1u : 0u, wsum, tot_rq);
         if (threadIdx.x == 0) {
             s_base[0] = tot_dep ? atomicAdd(&ctl->n_new, tot_dep) : 0u;
-            s_base[1] = tot_rq ? atomicAdd(&ctl->n_wq_next, tot_rq) : 0u;
+            s_base[1] = tot_rq ? atomicAdd(&d.aq_n[cur ^ 1u], tot_rq) : 0u;
         }
         __syncthreads();
-        if (rq) wq_next[s_base[1] + my_rq] = o;
+        if (rq) aq_next[s_base[1] + my_rq] = o;
         if (dep) {
             any_dep = true;
-            const uint32_t j = o.w;
             const uint32_t ns = n + s_base[0] + my_dep;
-            const int32_t e0 = (int32_t)o.z;
-            const uint32_t l0 = o.x - E0.w;
+            const int32_t e0 = (int32_t)R.z;
+            const uint32_t l0 = R.x - E0.w;
             const int32_t en0 = dr.z != NO_NEXT ? (int32_t)dr.z : -1;
             const uint32_t req0 = en0 >= 0 ? required_lane_of(ax0, E_LANES(E0)) : 0u;
             d.status[j] = ST_ACTIVE;
@@ -766,7 +791,7 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             S.rend[ns] = dr.y;
             S.ent[ns] = k + 1;
             set_cache_from(S, ns, E0, l0, sg0 != 0u, en0, En0, ax0);
-            d.map[o.y] = speed_byte(0.0f);
+            d.map[R.y] = speed_byte(0.0f);
             add_entry(d, e0, k + 1);
             atomicAdd(&cnt.c[P_DEPARTS], 1u);
         }
@@ -1000,6 +1025,32 @@ __global__ __launch_bounds__(1024) void k_lanechg(Dev d) {
 // ---------------------------------------------------------------------------
 // commit: lane changes into the map
 
+// the trips at departure-order positions [lo, hi) join their origin lanes'
+// waiting sets; a lane whose set was empty joins list aq[which] (exactly one
+// of the trips joining an empty set sees the empty head).  Runs after the
+// step's departures (the lane's bits, count and head are not touched
+// concurrently by anything else).  Helper block hb of nb.
+__device__ __forceinline__ void enqueue_part(const Dev &d, uint32_t lo, uint32_t hi, uint32_t which, uint32_t hb,
+                                             uint32_t nb) {
+    for (uint32_t q = lo + hb * blockDim.x + threadIdx.x; q < hi; q += nb * blockDim.x) {
+        const uint32_t j = d.dep_order[q];
+        const uint2 t = d.trip_ol[j];
+        atomicOr(&d.ol_bits[t.y >> 5], 1u << (t.y & 31));
+        atomicAdd(&d.ol_cnt[t.x], 1u);
+        if (atomicMin(&d.ol_head[t.x], t.y) == NO_NEXT) d.aq[which][atomicAdd(&d.aq_n[which], 1u)] = t.x;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_enqueue(Dev d, uint32_t lo, uint32_t hi, uint32_t which) {
+    enqueue_part(d, lo, hi, which, blockIdx.x, gridDim.x);
+}
+
+void launch_enqueue(const Dev &d, uint32_t lo, uint32_t hi, uint32_t which, hipStream_t s) {
+    if (hi <= lo) return;
+    const uint32_t n = hi - lo, g = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_enqueue, dim3(g), dim3(256), 0, s, d, lo, hi, which);
+}
+
 // end of step (first helper block of the commit launch): sums the per-block
 // arrival and event flags of the resolve phase over the G work blocks and
 // writes the next step's control block
@@ -1029,10 +1080,11 @@ __device__ __forceinline__ void end_part(const Dev &d, uint32_t G) {
         nx.n_alive = c.n_alive + (int64_t)c.n_new - (int64_t)s_arr;
         nx.n_slots = c.n_slots + c.n_new;
         nx.n_new = 0;
-        nx.dep_done = dep_hi_of(d, c.k);
-        nx.wq_cur = c.wq_cur ^ 1u;
-        nx.n_wq = c.n_wq_next;
-        nx.n_wq_next = 0;
+        // the trips due at the next step join the waiting sets in this launch
+        const uint32_t due_next = dep_hi_of(d, c.k + 1);
+        nx.dep_done = due_next;
+        nx.aq_cur = c.aq_cur ^ 1u;
+        nx.n_wq = c.n_wq - c.n_new + (due_next - c.dep_done);
         nx.k = c.k + 1;
         *d.ctrl_next = nx;
     }
@@ -1043,7 +1095,12 @@ __device__ __forceinline__ void end_part(const Dev &d, uint32_t G) {
 // lane changes are off); G = work blocks of the step's other kernels
 __global__ __launch_bounds__(1024) void k_commit(Dev d, uint32_t X, uint32_t G) {
     if (blockIdx.x < X) {
-        if (blockIdx.x == 0) end_part(d, G);
+        if (blockIdx.x == 0) {
+            end_part(d, G);
+        } else {
+            const Ctrl *ctl = d.ctrl;
+            enqueue_part(d, ctl->dep_done, dep_hi_of(d, ctl->k + 1), ctl->aq_cur ^ 1u, blockIdx.x - 1, X - 1);
+        }
         return;
     }
     const Ctrl *ctl = d.ctrl;
