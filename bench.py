@@ -39,8 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the move launch per active vehicle-step, besides what
 # the device counts into scan_bytes (lane-map cells scanned, one byte each;
 # the next edge's entry window near the stop line; a crossing vehicle's trip
-# id, claim word and request, 20; the departure requests' queue, trip and
-# entry-window reads, which run in the same launch):
+# id, claim word and request, 20; the departure requests' origin-lane list,
+# lane record, head, trip id and entry-window reads, which run in the same
+# launch):
 #   slot state read: meta, x, v (12) + the cached edge data the update needs:
 #     lane offset, cells | look-ahead | next-edge-blocked, speed limit, next
 #     lane offset (16)
