@@ -419,13 +419,25 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_reduce(MlpBwdArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= PAR_COUNT / 4) return;
     const float4 *p = reinterpret_cast<const float4 *>(a.part) + q;
-    float4 v = p[0];
-    for (int k = 1; k < a.n_split; ++k) {
-        const float4 u = p[(size_t)k * (PAR_COUNT / 4)];
-        v.x += u.x;
-        v.y += u.y;
-        v.z += u.z;
-        v.w += u.w;
+    // eight slices' loads in flight at a time, added in slice order
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k0 = 0; k0 < a.n_split; k0 += 8) {
+        float4 u[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (k0 + j < a.n_split) u[j] = p[(size_t)(k0 + j) * (PAR_COUNT / 4)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (k0 + j >= a.n_split) break;
+            if (k0 + j == 0) {
+                v = u[0];
+                continue;
+            }
+            v.x += u[j].x;
+            v.y += u[j].y;
+            v.z += u[j].z;
+            v.w += u[j].w;
+        }
     }
     const int e = 4 * q;
     const int L = e >= PAR_W[3] ? 3 : e >= PAR_W[2] ? 2 : e >= PAR_W[1] ? 1 : 0;
