@@ -57,8 +57,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 MOVE_TRAFFIC = {
     # profiles/k_move_regional_peak_counters.md
     ("regional-225k-2.82M", 19136, 20): {
-        "fetch_kib": 44321.11, "fetch_scale": 2.0, "write_kib": 24143.66, "write_scale": 1.0,
-        "kernels_sha256": "2d18b38956f2744337910bba4c72d37a9931a48c08ebe5a744b3396e8f98add0"},
+        "fetch_kib": 46557.80, "fetch_scale": 2.0, "write_kib": 24116.73, "write_scale": 1.0,
+        "kernels_sha256": "fc4ba2ba4ef0807fc653a92036e204fba89e89a1e1b8a58fc51f60ffcef94c5b"},
 }
 
 
