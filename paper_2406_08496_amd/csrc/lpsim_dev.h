@@ -84,6 +84,7 @@ struct Slots {
 };
 
 constexpr uint32_t NO_NEXT = 0xffffffffu;
+constexpr unsigned long long NO_HEAD = ~0ull;
 constexpr uint32_t CD_NEXT_BLOCKED = 1u << 31;  // the next edge accepts no entries
 constexpr uint32_t CD_SIGNAL = 1u << 30;        // the current edge ends at a signal serving it
 
@@ -144,20 +145,23 @@ struct Dev {
     //               holds only the end of the final segment)
     //   ol_trips    each lane's trips in increasing id, lane after lane
     //   ol_bits     one bit per ol_trips entry: due and not yet entered
-    //   ol_head[o]  position in ol_trips of the lane's lowest waiting trip,
-    //               NO_NEXT when none waits
+    //   ol_head[o]  the lane's lowest waiting trip: its position in ol_trips
+    //               << 32 | its trip id (NO_HEAD when none waits; the two
+    //               orders agree within a lane, so one 64-bit minimum
+    //               keeps both)
     //   ol_cnt[o]   waiting trips of the lane
     //   trip_ol[j]  {origin lane, position in ol_trips}
-    //   aq[2]       origin lanes with waiting trips: this step's list and the
-    //               next step's, counts in aq_n[2] (the move launch clears
-    //               the next one's count)
+    //   aq[2]       origin lanes with waiting trips, as {claim word, lane-map
+    //               offset, first edge, origin lane}: this step's list and
+    //               the next step's, counts in aq_n[2] (the move launch
+    //               clears the next one's count)
     const uint4 *ol_rec;
     const uint32_t *ol_trips;
     uint32_t *ol_bits;
-    uint32_t *ol_head;
+    unsigned long long *ol_head;
     uint32_t *ol_cnt;
     const uint2 *trip_ol;
-    uint32_t *aq[2];
+    uint4 *aq[2];
     uint32_t *aq_n;
     uint32_t n_ol;
     uint8_t *dclaim;      // [position in this step's lane list] the lane's request was made

@@ -401,7 +401,7 @@ static int32_t reset_run_state(lpsim_ctx *c) {
     HIPCHK(c, hipMemset(d.arrival, 0xff, (N + 1) * 4));
     HIPCHK(c, hipMemset(d.dclaim, 0, (size_t)d.n_ol + 1));
     HIPCHK(c, hipMemset(d.ol_bits, 0, (N / 32 + 1) * 4));
-    HIPCHK(c, hipMemset(d.ol_head, 0xff, ((size_t)d.n_ol + 1) * 4));
+    HIPCHK(c, hipMemset(d.ol_head, 0xff, ((size_t)d.n_ol + 1) * 8));
     HIPCHK(c, hipMemset(d.ol_cnt, 0, ((size_t)d.n_ol + 1) * 4));
     HIPCHK(c, hipMemset(d.aq_n, 0, 2 * 4));
     HIPCHK(c, hipMemset(d.ecnt, 0, E * 4));
@@ -1311,8 +1311,8 @@ struct SnapHeader {
 static size_t snap_size(const lpsim_ctx *c, uint64_t n_slots, uint64_t n_aq) {
     const size_t N = (size_t)c->n_trips, E = (size_t)c->n_edges, B = (size_t)c->dp.n_bins;
     return sizeof(SnapHeader) + sizeof(Ctrl) + (size_t)PART_ROWS * NPART * 8 + c->map_bytes + (N + 1) * 5 +
-           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (N / 32 + 1) * 4 + ((size_t)c->d.n_ol + 1) * 8 +
-           (size_t)n_aq * 4;
+           E * 12 + E * B * 24 + (size_t)n_slots * 56 + (N / 32 + 1) * 4 + ((size_t)c->d.n_ol + 1) * 12 +
+           (size_t)n_aq * 16;
 }
 
 // origin lanes in the live waiting list
@@ -1382,9 +1382,9 @@ int32_t lpsim_save_state(lpsim_ctx *c, void *buf, size_t bytes) {
     if ((rc = get(S.tlb, n * 4))) return rc;
     if ((rc = get(S.tgt, n * 4))) return rc;
     if ((rc = get(d.ol_bits, (N / 32 + 1) * 4))) return rc;
-    if ((rc = get(d.ol_head, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = get(d.ol_head, ((size_t)d.n_ol + 1) * 8))) return rc;
     if ((rc = get(d.ol_cnt, ((size_t)d.n_ol + 1) * 4))) return rc;
-    if ((rc = get(d.aq[ct.aq_cur & 1u], (size_t)n_aq * 4))) return rc;
+    if ((rc = get(d.aq[ct.aq_cur & 1u], (size_t)n_aq * 16))) return rc;
     return LPSIM_OK;
 }
 
@@ -1437,9 +1437,9 @@ int32_t lpsim_restore_state(lpsim_ctx *c, const void *buf, size_t bytes) {
     if ((rc = put(S.tlb, n * 4))) return rc;
     if ((rc = put(S.tgt, n * 4))) return rc;
     if ((rc = put(d.ol_bits, (N / 32 + 1) * 4))) return rc;
-    if ((rc = put(d.ol_head, ((size_t)d.n_ol + 1) * 4))) return rc;
+    if ((rc = put(d.ol_head, ((size_t)d.n_ol + 1) * 8))) return rc;
     if ((rc = put(d.ol_cnt, ((size_t)d.n_ol + 1) * 4))) return rc;
-    if ((rc = put(d.aq[0], (size_t)h.n_aq * 4))) return rc;
+    if ((rc = put(d.aq[0], (size_t)h.n_aq * 16))) return rc;
     const uint32_t aq_n[2] = {(uint32_t)h.n_aq, 0u};
     HIPCHK(c, hipMemcpy(d.aq_n, aq_n, sizeof aq_n, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(d.claims, 0xff, (size_t)c->n_lane_slots * 4));

@@ -532,9 +532,8 @@ __device__ __forceinline__ void set_cache(const Dev &d, const Slots &S, uint32_t
 // move: it reads the same step-k map and only adds claims.  One request per
 // origin lane with waiting trips, for its lowest trip id: the lane's trips
 // share the entry window and the first edge, so no other of them can win.
-// Its bytes (list entry 4, lane record 16, head 4, trip id 4, the first
-// edge's flags 4, the entry window W, the request flag 1) count into row
-// MAX_BLOCKS + hb.
+// Its bytes (list entry 16, head 8, the first edge's flags 4, the entry
+// window W, the request flag 1) count into row MAX_BLOCKS + hb.
 __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X) {
     __shared__ BlockCounts cnt;
     counts_init(&cnt);
@@ -543,18 +542,17 @@ __device__ __forceinline__ void cand_part(const Dev &d, uint32_t hb, uint32_t X)
     // the next step's lane list starts empty (last read by the previous step)
     if (hb == 0 && threadIdx.x == 0) d.aq_n[cur ^ 1u] = 0u;
     const uint32_t nc = d.aq_n[cur];
-    const uint32_t *aq = d.aq[cur];
+    const uint4 *aq = d.aq[cur];
     const uint32_t W = (uint32_t)d.p.W;
     uint32_t bytes = 0;
     for (uint32_t q = hb * blockDim.x + threadIdx.x; q < nc; q += X * blockDim.x) {
-        const uint32_t o = aq[q];
-        const uint4 R = d.ol_rec[o];
-        const uint32_t h = d.ol_head[o];  // a listed lane has a waiting trip
-        const uint32_t j = h != NO_NEXT ? d.ol_trips[h] : NO_NEXT;
-        const bool ok = h != NO_NEXT && !(d.aux[R.z] & AUX_BLOCKED) && first_occ(d.map, R.y, 0, (int32_t)W - 1) < 0;
+        const uint4 A = aq[q];
+        const unsigned long long head = d.ol_head[A.w];  // a listed lane has a waiting trip
+        const uint32_t j = (uint32_t)head;
+        const bool ok = head != NO_HEAD && !(d.aux[A.z] & AUX_BLOCKED) && first_occ(d.map, A.y, 0, (int32_t)W - 1) < 0;
         d.dclaim[q] = ok ? 1 : 0;
-        if (ok) atomicMin(&d.claims[R.x], j);
-        bytes += 4u + 16u + 4u + 4u + 4u + W + 1u;
+        if (ok) atomicMin(&d.claims[A.x], j);
+        bytes += 16u + 8u + 4u + W + 1u;
     }
     if (bytes) atomicAdd(&cnt.c[P_SCAN], bytes);
     counts_flush(d, &cnt, MAX_BLOCKS + hb);
@@ -713,37 +711,37 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
     const int32_t k = ctl->k;
     const uint32_t cur = ctl->aq_cur;
     const uint32_t nc = d.aq_n[cur];
-    const uint32_t *aq = d.aq[cur];
-    uint32_t *aq_next = d.aq[cur ^ 1u];
+    const uint4 *aq = d.aq[cur];
+    uint4 *aq_next = d.aq[cur ^ 1u];
     const uint32_t n = ctl->n_slots;
     const Slots S = ctl->cur ? d.buf[1] : d.buf[0];
     bool any_dep = false;
     for (uint32_t pass0 = hb * blockDim.x; pass0 < nc; pass0 += X * blockDim.x) {
         const uint32_t q = pass0 + threadIdx.x;
         bool dep = false, rq = false;
-        uint32_t o = 0, j = 0;
-        uint4 R = make_uint4(0, 0, 0, 0);
+        uint32_t j = 0;
+        uint4 A = make_uint4(0, 0, 0, 0);
         // a winner's edge records and route data, read before the block
         // scans: with the claim word for lanes that made a request, then the
         // second edge's record and aux word for winners
         uint4 E0 = make_uint4(0, 0, 0, 0), dr = make_uint4(0, 0, NO_NEXT, 0), En0 = make_uint4(0, 0, 0, 0);
         uint32_t ax0 = 0, sg0 = 0;
         if (q < nc) {
-            o = aq[q];
-            R = d.ol_rec[o];
-            const uint32_t h = d.ol_head[o];
+            A = aq[q];
+            const uint32_t o = A.w;
+            const unsigned long long head = d.ol_head[o];
             uint32_t wc = d.ol_cnt[o];
             uint32_t claimed = d.dclaim[q];
-            j = h != NO_NEXT ? d.ol_trips[h] : NO_NEXT;
-            uint32_t cw = d.claims[R.x];
+            uint32_t cw = d.claims[A.x];
+            j = (uint32_t)head;
             if (claimed) {
-                E0 = d.edge[R.z];
+                E0 = d.edge[A.z];
                 dr = d.dep_rec[j];
-                if (d.sig != nullptr) sg0 = d.sig[R.z].x;
+                if (d.sig != nullptr) sg0 = d.sig[A.z].x;
             }
             ISSUED_TOGETHER4(claimed, cw, E0.x, dr.x);
             if (claimed && cw == j) {
-                d.claims[R.x] = 0xffffffffu;
+                d.claims[A.x] = 0xffffffffu;
                 dep = true;
                 if (dr.z != NO_NEXT) {
                     En0 = d.edge[dr.z];
@@ -751,14 +749,15 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
                 }
                 // leave the set: clear the bit (a word may hold bits of a
                 // neighbouring lane), find the next waiting trip
+                const uint32_t h = (uint32_t)(head >> 32);
                 atomicAnd(&d.ol_bits[h >> 5], ~(1u << (h & 31)));
                 wc -= 1u;
                 d.ol_cnt[o] = wc;
                 const uint32_t nh = wc ? next_waiting(d, h, d.ol_rec[o + 1].w) : NO_NEXT;
-                d.ol_head[o] = nh;
+                d.ol_head[o] = nh != NO_NEXT ? ((unsigned long long)nh << 32) | d.ol_trips[nh] : NO_HEAD;
                 rq = nh != NO_NEXT;
             } else {
-                rq = h != NO_NEXT;
+                rq = head != NO_HEAD;
             }
             // every other trip of a lane that asked lost its request
             if (claimed && wc) atomicAdd(&cnt.c[P_LOST], wc);
@@ -772,12 +771,12 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             s_base[1] = tot_rq ? atomicAdd(&d.aq_n[cur ^ 1u], tot_rq) : 0u;
         }
         __syncthreads();
-        if (rq) aq_next[s_base[1] + my_rq] = o;
+        if (rq) aq_next[s_base[1] + my_rq] = A;
         if (dep) {
             any_dep = true;
             const uint32_t ns = n + s_base[0] + my_dep;
-            const int32_t e0 = (int32_t)R.z;
-            const uint32_t l0 = R.x - E0.w;
+            const int32_t e0 = (int32_t)A.z;
+            const uint32_t l0 = A.x - E0.w;
             const int32_t en0 = dr.z != NO_NEXT ? (int32_t)dr.z : -1;
             const uint32_t req0 = en0 >= 0 ? required_lane_of(ax0, E_LANES(E0)) : 0u;
             d.status[j] = ST_ACTIVE;
@@ -791,7 +790,7 @@ __device__ __forceinline__ void depart_part(const Dev &d, uint32_t hb, uint32_t 
             S.rend[ns] = dr.y;
             S.ent[ns] = k + 1;
             set_cache_from(S, ns, E0, l0, sg0 != 0u, en0, En0, ax0);
-            d.map[R.y] = speed_byte(0.0f);
+            d.map[A.y] = speed_byte(0.0f);
             add_entry(d, e0, k + 1);
             atomicAdd(&cnt.c[P_DEPARTS], 1u);
         }
@@ -1037,7 +1036,10 @@ __device__ __forceinline__ void enqueue_part(const Dev &d, uint32_t lo, uint32_t
         const uint2 t = d.trip_ol[j];
         atomicOr(&d.ol_bits[t.y >> 5], 1u << (t.y & 31));
         atomicAdd(&d.ol_cnt[t.x], 1u);
-        if (atomicMin(&d.ol_head[t.x], t.y) == NO_NEXT) d.aq[which][atomicAdd(&d.aq_n[which], 1u)] = t.x;
+        if (atomicMin(&d.ol_head[t.x], ((unsigned long long)t.y << 32) | j) == NO_HEAD) {
+            const uint4 R = d.ol_rec[t.x];
+            d.aq[which][atomicAdd(&d.aq_n[which], 1u)] = make_uint4(R.x, R.y, R.z, t.x);
+        }
     }
 }
 
