@@ -1034,12 +1034,11 @@ __device__ __forceinline__ void enqueue_part(const Dev &d, uint32_t lo, uint32_t
     for (uint32_t q = lo + hb * blockDim.x + threadIdx.x; q < hi; q += nb * blockDim.x) {
         const uint32_t j = d.dep_order[q];
         const uint2 t = d.trip_ol[j];
+        const uint4 R = d.ol_rec[t.x];  // issued beside the head's minimum, used by one trip per lane
         atomicOr(&d.ol_bits[t.y >> 5], 1u << (t.y & 31));
         atomicAdd(&d.ol_cnt[t.x], 1u);
-        if (atomicMin(&d.ol_head[t.x], ((unsigned long long)t.y << 32) | j) == NO_HEAD) {
-            const uint4 R = d.ol_rec[t.x];
+        if (atomicMin(&d.ol_head[t.x], ((unsigned long long)t.y << 32) | j) == NO_HEAD)
             d.aq[which][atomicAdd(&d.aq_n[which], 1u)] = make_uint4(R.x, R.y, R.z, t.x);
-        }
     }
 }
 
