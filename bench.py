@@ -57,8 +57,8 @@ MOVE_FIXED_BYTES = 12 + 16 + 12
 MOVE_TRAFFIC = {
     # profiles/k_move_regional_peak_counters.md
     ("regional-225k-2.82M", 19136, 20): {
-        "fetch_kib": 46557.80, "fetch_scale": 2.0, "write_kib": 24116.73, "write_scale": 1.0,
-        "kernels_sha256": "fc4ba2ba4ef0807fc653a92036e204fba89e89a1e1b8a58fc51f60ffcef94c5b"},
+        "fetch_kib": 43035.53, "fetch_scale": 2.0, "write_kib": 24110.31, "write_scale": 1.0,
+        "kernels_sha256": "9ed09b628f65469f4638b9ea73974b0949f5934106e95f402f81d8475339b5c3"},
 }
 
 
