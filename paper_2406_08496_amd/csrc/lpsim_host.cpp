@@ -557,9 +557,12 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         }
     }
     // origin lanes (the lanes trips start on), numbered in claim-word order,
-    // each with its trips in increasing id
+    // each with its trips in increasing id: counted and filled on all host
+    // threads (relaxed atomic counters), then each lane's few trips sorted
     std::vector<uint32_t> ol_of((size_t)c->n_lane_slots + 1, 0);  // trips per claim word, then lane number
-    for (int64_t t = 0; t < N; ++t) ol_of[orig[(size_t)t].x]++;
+    host_parallel(N, [&](int64_t lo, int64_t hi) {
+        for (int64_t t = lo; t < hi; ++t) __atomic_fetch_add(&ol_of[orig[(size_t)t].x], 1u, __ATOMIC_RELAXED);
+    });
     std::vector<uint4> ol_rec;
     uint32_t n_ol = 0;
     {
@@ -580,15 +583,22 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     std::vector<uint2> trip_ol((size_t)std::max<int64_t>(N, 1));
     {
         std::vector<uint32_t> fill(n_ol, 0);
-        for (int64_t t = 0; t < N; ++t) {
-            const uint4 o = orig[(size_t)t];
-            const uint32_t l = ol_of[o.x];
-            ol_rec[l].y = o.y;
-            ol_rec[l].z = o.z;
-            const uint32_t pos = ol_rec[l].w + fill[l]++;
-            ol_trips[pos] = (uint32_t)t;
-            trip_ol[(size_t)t] = make_uint2(l, pos);
-        }
+        host_parallel(N, [&](int64_t lo, int64_t hi) {
+            for (int64_t t = lo; t < hi; ++t) {
+                const uint32_t l = ol_of[orig[(size_t)t].x];
+                ol_trips[ol_rec[l].w + __atomic_fetch_add(&fill[l], 1u, __ATOMIC_RELAXED)] = (uint32_t)t;
+            }
+        });
+        host_parallel(n_ol, [&](int64_t lo, int64_t hi) {
+            for (int64_t l = lo; l < hi; ++l) {
+                const uint32_t beg = ol_rec[(size_t)l].w, end = ol_rec[(size_t)l + 1].w;
+                std::sort(ol_trips.begin() + beg, ol_trips.begin() + end);
+                const uint4 o = orig[ol_trips[beg]];
+                ol_rec[(size_t)l].y = o.y;
+                ol_rec[(size_t)l].z = o.z;
+                for (uint32_t p = beg; p < end; ++p) trip_ol[ol_trips[p]] = make_uint2((uint32_t)l, p);
+            }
+        });
     }
     std::vector<uint64_t> seeds(S);
     std::vector<uint32_t> tbase(S);
