@@ -198,6 +198,36 @@ def test_save_restore_bit_exact(Sim):
     assert_same_stats(b.edge_stats(), sa, "restored")
 
 
+def test_crowded_origin_lanes(Sim):
+    """Hundreds of trips waiting on the same few origin lanes, falling due
+    out of id order (a lower id often becomes due after higher ids already
+    wait), so each lane's head moves back and forth, and the waiting sets run
+    over many words, some shared by two lanes; a snapshot is taken while the
+    sets are full.  Compared with the oracle at every step."""
+    case("crowded origin lanes, 700 trips on 3 lanes, snapshot mid-queue")
+    rng = np.random.default_rng(41)
+    n = 700
+    # edge 0 (2 lanes) and edge 3 (1 lane) feed the corridor; start lane of
+    # a trip on edge 0 is its id mod 2, so two lanes interleave their ids
+    routes = [[0, 1, 2] if i % 3 else [3, 1, 2] for i in range(n)]
+    departs = rng.integers(0, 120, size=n)
+    departs[::7] = 5  # bursts at one step
+    inst = synth.line_instance([60, 400, 300], [13.4, 17.9, 22.4], [2, 1, 2], departs.tolist(), routes,
+                               extra_edges=[(4, 1, 40.0, 11.2, 1)])
+    gpu, ref = run_pair(Sim, inst, 260, 1)
+    c = ref.counters()
+    assert c["claims_lost"] > 1000 and c["waiting"] > 100
+    snap = gpu.save_state()
+    gpu.step(400)
+    ref.step(400)
+    assert_same_state(gpu.vehicles(), ref.vehicles(), "step 660")
+    b = Sim().load(inst)
+    b.restore_state(snap)
+    b.step(400)
+    assert_same_state(b.vehicles(), ref.vehicles(), "restored, step 660")
+    assert_same_counters(b.counters(), ref.counters(), "restored, step 660")
+
+
 def test_regional_small_full_horizon(Sim):
     case("regional planar graph at 1% scale, full horizon, compare every 1200 steps")
     inst = synth.regional(0.01)
