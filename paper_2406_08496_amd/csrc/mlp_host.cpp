@@ -90,7 +90,7 @@ int32_t lpsim_mlp_loss_grad(const float *y, const float *target, const uint8_t *
 }
 
 size_t lpsim_mlp_workspace_bytes(int64_t n, int32_t n_split) {
-    if (n < 0 || n_split < 1) return 0;
+    if (n < 0 || n_split < 1 || n_split > 1024) return 0;
     return bwd_workspace_bytes(n, n_split);
 }
 
