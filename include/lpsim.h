@@ -344,14 +344,16 @@ int32_t lpsim_mlp_loss_grad(const float *y, const float *target, const uint8_t *
 
 /* Bytes of the `workspace` that lpsim_mlp_backward needs for n rows in
  * n_split batch slices: the data gradients and the input in fragment order,
- * then the slices' binary32 partial sums.  0 for invalid arguments. */
+ * then the slices' binary32 partial sums.  0 for invalid arguments (n < 0,
+ * n_split outside 1..1024). */
 size_t lpsim_mlp_workspace_bytes(int64_t n, int32_t n_split);
 
 /* Backward pass of the binary32-accumulated perceptron for a batch of n rows:
  * x[n][32] and h (3 pointers) as produced by the forward, dz_out[n][16]
  * bfloat16 output gradient (row-major), w (4 pointers, the "w" copies).
- * Writes dwt (4 pointers, binary32 [out_l][in_l]) and db (4 pointers).  The weight gradients are summed over the rows of each of
- * n_split (1..1024) batch slices, then over the slices in order:
+ * Writes dwt (4 pointers, binary32 [out_l][in_l]) and db (4 pointers).
+ * The weight gradients are summed over the rows of each of n_split
+ * (1..1024) batch slices, then over the slices in order:
  * deterministic for fixed n_split.  x, dz_out, every h[l] and w[l], and
  * workspace (lpsim_mlp_workspace_bytes(n, n_split) bytes, caller-owned) must
  * be 16-byte aligned.  n = 0 writes zero gradients (kernels only, no

@@ -92,6 +92,7 @@ def test_mlp_entry_points_validate_arguments():
     assert lib.lpsim_mlp_workspace_bytes(1001, 3) == 816 * 1024 * 2 + 3 * 144_144 * 4
     assert lib.lpsim_mlp_workspace_bytes(0, 1) == 144_144 * 4
     assert lib.lpsim_mlp_workspace_bytes(10, 0) == 0
+    assert lib.lpsim_mlp_workspace_bytes(10, 1025) == 0
     assert lib.lpsim_mlp_workspace_bytes(-1, 4) == 0
     # argument checks run on the host, before any launch
     assert lib.lpsim_mlp_backward(None, None, None, None, None, None, None, 1, 10, None) == -1
