@@ -41,12 +41,14 @@ HBM_PEAK_GBS = 8000.0
 # the next edge's entry window near the stop line; a crossing vehicle's trip
 # id, claim word and request, 20; the departure requests' origin-lane list,
 # lane record, head, trip id and entry-window reads, which run in the same
-# launch):
-#   slot state read: meta, x, v (12) + the cached edge data the update needs:
-#     lane offset, cells | look-ahead | next-edge-blocked, speed limit, next
-#     lane offset (16)
-#   slot state write: x, v, meta (12)
-MOVE_FIXED_BYTES = 12 + 16 + 12
+# launch).  The fixed part is what the method must move per vehicle-step, not
+# what this kernel happens to read:
+#   state read: x, v, edge, lane, status, route index (18)
+#   state write: x, v (8)
+# The kernel actually reads 28 bytes (meta, x, v and 16 bytes of edge data
+# cached in the slot, in place of the edge id and route index) and writes 12
+# (x, v, meta); the counted HBM traffic shows what it moves.
+MOVE_FIXED_BYTES = 18 + 8
 
 # HBM traffic of one k_move launch, from two rocprofv3 --pmc runs of the
 # benchmark command itself (FETCH_SIZE, WRITE_SIZE: KiB per dispatch, mean

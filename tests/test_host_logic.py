@@ -27,8 +27,8 @@ def test_bench_refuses_more_than_one_gpu():
 def test_bench_byte_model_and_traffic_key():
     import bench
 
-    # 28 bytes of state read and 12 written per vehicle-step
-    assert bench.MOVE_FIXED_BYTES == 40
+    # the method's 18 bytes of state read and 8 written per vehicle-step
+    assert bench.MOVE_FIXED_BYTES == 26
     src = os.path.join(ROOT, "paper_2406_08496_amd", "csrc", "lpsim_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for key, m in bench.MOVE_TRAFFIC.items():
