@@ -173,6 +173,45 @@ def test_backward_through_forward_and_empty(torch):
         assert torch.count_nonzero(t).item() == 0
 
 
+def test_full_size_sampled(torch):
+    """The benchmark's inference batch (2,200,000 rows) with the default
+    slice count: sampled forward rows against the oracle within its bound,
+    and the output layer's weight and bias gradients (whose inputs, dz_out and
+    the kept last hidden layer, are exact) against float64 sums over all rows
+    within the binary32 bound of an n/S + S + 32 chain, for sampled weights
+    and every bias."""
+    case("mlp full size, 2.2M rows, sampled")
+    from paper_2406_08496_amd.surrogate import EdgeMLP
+
+    n = 2_200_000
+    wt, b = mlp.init_params(12)
+    rng = np.random.default_rng(13)
+    x = mlp.bf16(rng.normal(size=(n, 32)).astype(np.float32))
+    net = EdgeMLP(wt, b)
+    xt = bf(torch, x)
+    y, hs = net.forward(xt, keep=True)
+    rows = np.sort(rng.choice(n, 3000, replace=False))
+    y_ref, hs_ref = mlp.forward(x[rows], wt, b)
+    bound = mlp.forward_bound(x[rows], wt, b, y_ref, hs_ref)
+    err = np.abs(to_np(y[torch.from_numpy(rows).cuda()]) - y_ref)
+    assert np.all(err <= bound)
+    dz = mlp.bf16(rng.normal(size=(n, 16)).astype(np.float32) * 1e-3)
+    dzt = bf(torch, dz)
+    net.backward(xt, hs, dzt)
+    torch.cuda.synchronize()
+    S = net.splits(n)
+    g = mlp.gamma(n // S + S + 32)
+    h2 = EdgeMLP.hidden_rows(hs, n)[2]
+    gw, gb = to_np(net.g_w[3]), to_np(net.g_b[3])
+    db_ref = dz.sum(axis=0)
+    assert np.all(np.abs(gb - db_ref) <= g * np.abs(dz).sum(axis=0) + 1e-30)
+    for i in rng.choice(256, 12, replace=False):
+        col = to_np(h2[:, int(i)].contiguous())
+        ref = dz.T @ col
+        err = np.abs(gw[:, i] - ref)
+        assert np.all(err <= g * (np.abs(dz).T @ np.abs(col)) + 1e-30), f"dW layer 4, input {i}"
+
+
 def test_adam_matches_float64(torch):
     case("adam, 5 steps")
     from paper_2406_08496_amd.surrogate import EdgeMLP
