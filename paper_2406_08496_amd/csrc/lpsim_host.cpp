@@ -57,6 +57,10 @@ struct lpsim_ctx {
 
     // trips
     int64_t n_trips = 0;
+    // page-locked staging of the translated routes, kept across loads (an
+    // assignment loop reloads every iteration)
+    uint32_t *route_pin = nullptr;
+    size_t route_pin_cap = 0;
     std::vector<int64_t> trip_off;
     bool have_trips = false;
     uint32_t slot_cap = 0;
@@ -450,72 +454,82 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
         if (in.trip_off[s + 1] < in.trip_off[s]) return fail(c, LPSIM_EINVAL, "trip offsets decrease");
     const int64_t N = in.trip_off[S];
     if (N > 0x7ffffffeLL) return fail(c, LPSIM_ECAPACITY, "more than 2^31-2 trips");
-    // validate routes and build absolute offsets
+    // absolute offsets, then the routes checked (edge ids in range,
+    // contiguous) and translated to internal ids in one pass on all host
+    // threads, straight into the page-locked staging buffer
     std::vector<uint32_t> roff((size_t)N + 1);
     uint64_t total = 0;
-    const int64_t *ro = in.route_offsets;
-    for (int32_t s = 0; s < S; ++s) {
-        const int64_t t0 = in.trip_off[s], nt = in.trip_off[s + 1] - t0;
-        const int32_t eb = c->edge_off[s], ne = c->edge_off[s + 1] - eb;
-        if (ro[0] != 0) return fail(c, LPSIM_EINVAL, "scenario %d: route offsets must start at 0", s);
-        for (int64_t t = 0; t < nt; ++t) {
-            const int64_t a = ro[t], b = ro[t + 1];
-            if (b <= a) return fail(c, LPSIM_EINVAL, "trip %lld has an empty route", (long long)(t0 + t));
-            if (in.depart[t0 + t] < 0) return fail(c, LPSIM_EINVAL, "trip %lld departs before 0", (long long)(t0 + t));
-            roff[(size_t)(t0 + t)] = (uint32_t)(total + (uint64_t)a);
+    {
+        const int64_t *ro = in.route_offsets;
+        for (int32_t s = 0; s < S; ++s) {
+            const int64_t t0 = in.trip_off[s], nt = in.trip_off[s + 1] - t0;
+            if (ro[0] != 0) return fail(c, LPSIM_EINVAL, "scenario %d: route offsets must start at 0", s);
+            for (int64_t t = 0; t < nt; ++t) {
+                const int64_t a0 = ro[t], b0 = ro[t + 1];
+                if (b0 <= a0) return fail(c, LPSIM_EINVAL, "trip %lld has an empty route", (long long)(t0 + t));
+                if (in.depart[t0 + t] < 0)
+                    return fail(c, LPSIM_EINVAL, "trip %lld departs before 0", (long long)(t0 + t));
+                roff[(size_t)(t0 + t)] = (uint32_t)(total + (uint64_t)a0);
+            }
+            total += (uint64_t)ro[nt];
+            if (total > 0xfffffff0ull) return fail(c, LPSIM_ECAPACITY, "more than 2^32-16 route entries");
+            ro += nt + 1;
         }
-        const int64_t len = ro[nt];
-        const int32_t *re = in.route_edges + total;
-        // edge ids in range and routes contiguous, checked on all host
-        // threads; the lowest failing trip is reported
-        std::atomic<int64_t> bad_range{INT64_MAX}, bad_gap{INT64_MAX};
-        host_parallel(nt, [&](int64_t t_lo, int64_t t_hi) {
-            for (int64_t t = t_lo; t < t_hi; ++t) {
-                for (int64_t j = ro[t]; j < ro[t + 1]; ++j) {
-                    const int32_t e = re[j];
-                    if (e < 0 || e >= ne) {
-                        int64_t cur = bad_range.load();
-                        while (t < cur && !bad_range.compare_exchange_weak(cur, t)) {
+        roff[(size_t)N] = (uint32_t)total;
+    }
+    if (c->route_pin_cap < total + 1) {
+        if (c->route_pin) HIPCHK(c, hipHostFree(c->route_pin));
+        c->route_pin = nullptr;
+        c->route_pin_cap = 0;
+        void *p = nullptr;
+        const size_t cap = (size_t)(total + 1) + (size_t)(total + 1) / 8;  // room for longer routes later
+        if (hipHostMalloc(&p, cap * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess || !p)
+            return fail(c, LPSIM_ENOMEM, "page-locked staging of %zu route entries failed", cap);
+        c->route_pin = static_cast<uint32_t *>(p);
+        c->route_pin_cap = cap;
+    }
+    uint32_t *route = c->route_pin;
+    {
+        const int64_t *ro = in.route_offsets;
+        const int32_t *re = in.route_edges;
+        uint32_t *out = route;
+        for (int32_t s = 0; s < S; ++s) {
+            const int64_t t0 = in.trip_off[s], nt = in.trip_off[s + 1] - t0;
+            const int32_t eb = c->edge_off[s], ne = c->edge_off[s + 1] - eb;
+            // the lowest failing trip is reported
+            std::atomic<int64_t> bad_range{INT64_MAX}, bad_gap{INT64_MAX};
+            host_parallel(nt, [&](int64_t t_lo, int64_t t_hi) {
+                for (int64_t t = t_lo; t < t_hi; ++t) {
+                    for (int64_t j = ro[t]; j < ro[t + 1]; ++j) {
+                        const int32_t e = re[j];
+                        if (e < 0 || e >= ne) {
+                            int64_t cur = bad_range.load();
+                            while (t < cur && !bad_range.compare_exchange_weak(cur, t)) {
+                            }
+                            break;
                         }
-                        break;
-                    }
-                    if (j > ro[t] && c->dst_g[eb + re[j - 1]] != c->src_g[eb + e]) {
-                        int64_t cur = bad_gap.load();
-                        while (t < cur && !bad_gap.compare_exchange_weak(cur, t)) {
+                        if (j > ro[t] && c->dst_g[eb + re[j - 1]] != c->src_g[eb + e]) {
+                            int64_t cur = bad_gap.load();
+                            while (t < cur && !bad_gap.compare_exchange_weak(cur, t)) {
+                            }
+                            break;
                         }
-                        break;
+                        out[j] = (uint32_t)c->int_of_ext[eb + e];
                     }
                 }
-            }
-        });
-        if (bad_range.load() != INT64_MAX || bad_gap.load() != INT64_MAX) {
-            if (bad_range.load() <= bad_gap.load())
-                return fail(c, LPSIM_EINVAL, "trip %lld: edge id out of range", (long long)(t0 + bad_range.load()));
-            return fail(c, LPSIM_EINVAL, "trip %lld: route is not contiguous", (long long)(t0 + bad_gap.load()));
-        }
-        total += (uint64_t)len;
-        if (total > 0xfffffff0ull) return fail(c, LPSIM_ECAPACITY, "more than 2^32-16 route entries");
-        ro += nt + 1;
-    }
-    roff[(size_t)N] = (uint32_t)total;
-    std::vector<uint32_t> route((size_t)total + 1);
-    {
-        size_t p = 0;
-        // translate local ids to internal ids scenario by scenario
-        const int64_t *ro2 = in.route_offsets;
-        for (int32_t s = 0; s < S; ++s) {
-            const int64_t nt = in.trip_off[s + 1] - in.trip_off[s];
-            const int32_t eb = c->edge_off[s];
-            const int64_t len = ro2[nt];
-            const int32_t *re = in.route_edges + p;
-            uint32_t *out = route.data() + p;
-            host_parallel(len, [&](int64_t lo, int64_t hi) {
-                for (int64_t j = lo; j < hi; ++j) out[j] = (uint32_t)c->int_of_ext[eb + re[j]];
             });
-            p += (size_t)len;
-            ro2 += nt + 1;
+            if (bad_range.load() != INT64_MAX || bad_gap.load() != INT64_MAX) {
+                if (bad_range.load() <= bad_gap.load())
+                    return fail(c, LPSIM_EINVAL, "trip %lld: edge id out of range",
+                                (long long)(t0 + bad_range.load()));
+                return fail(c, LPSIM_EINVAL, "trip %lld: route is not contiguous", (long long)(t0 + bad_gap.load()));
+            }
+            const int64_t len = ro[nt];
+            re += len;
+            out += len;
+            ro += nt + 1;
         }
-        route[(size_t)total] = 0;
+        route[total] = 0;
     }
     // departure order and the count of trips due by each step
     int32_t maxdep = -1;
@@ -616,7 +630,7 @@ static int32_t build_trips(lpsim_ctx *c, const TripIn &in) {
     c->slot_cap = (uint32_t)cap;
     const uint32_t *route_d, *roff_d, *order_d, *dephi_d, *tbase_d;
     const uint64_t *seeds_d;
-    if ((rc = upload(c, *(uint32_t **)&route_d, route.data(), route.size(), c->trip_allocs))) return rc;
+    if ((rc = upload(c, *(uint32_t **)&route_d, route, (size_t)total + 1, c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint32_t **)&roff_d, roff.data(), roff.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint32_t **)&order_d, order.data(), order.size(), c->trip_allocs))) return rc;
     if ((rc = upload(c, *(uint32_t **)&dephi_d, dep_hi.data(), dep_hi.size(), c->trip_allocs))) return rc;
@@ -936,6 +950,7 @@ void lpsim_destroy(lpsim_ctx *c) {
     if (c->last) (void)hipStreamSynchronize(c->last);
     if (c->own) (void)hipStreamSynchronize(c->own);
     release_net(c);
+    if (c->route_pin) (void)hipHostFree(c->route_pin);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
