@@ -62,9 +62,13 @@ class Router:
             self.lib.lpsim_router_destroy(self._h)
             self._h = None
 
-    def routes(self, cost, origin, dest, old=None, take_new=None, timings=None):
+    def routes(self, cost, origin, dest, old=None, take_new=None, timings=None, out=None):
         """Routes for the trips: (offsets, edges); `timings` (a dict) gets
-        the seconds of the tree solve and of writing the routes added."""
+        the seconds of the tree solve and of writing the routes added.  With
+        `out` (int32, not the old routes' memory) the edges are written there
+        when it is large enough, and `edges` is a view of it; otherwise of a
+        new array with some room to spare, whose `.base` can be passed as
+        `out` next time (no fresh pages to fault in for a reused buffer)."""
         t0 = time.perf_counter()
         cost = np.ascontiguousarray(cost, np.float64)
         origin = np.ascontiguousarray(origin, np.int32)
@@ -89,7 +93,12 @@ class Router:
         rc = self.lib.lpsim_router_fill(self._h, _p(oo), _p(oe), _p(tk), _p(off), None)
         if rc:
             raise LpsimError(rc, "router fill")
-        edges = np.empty(max(int(off[-1]), 1), np.int32)
+        total = max(int(off[-1]), 1)
+        if (out is not None and out.dtype == np.int32 and out.ndim == 1 and out.flags.c_contiguous
+                and len(out) >= total and (oe is None or not np.may_share_memory(out, oe))):
+            edges = out
+        else:
+            edges = np.empty(total + (total // 16 if out is not None else 0), np.int32)
         rc = self.lib.lpsim_router_fill(self._h, _p(oo), _p(oe), _p(tk), _p(off), _p(edges))
         if rc:
             raise LpsimError(rc, "router fill")
@@ -127,6 +136,7 @@ class Assignment:
         self.origin = inst.meta["origin"]
         self.dest = inst.meta["dest"]
         self.timings = {}
+        self._new_route_buffers()
         self.progress = None  # optional callable(dict) after each iteration
 
     # -- evaluation by simulation -------------------------------------------
@@ -166,16 +176,37 @@ class Assignment:
         if self.progress:
             self.progress(dict(rec, wall_s=round(time.perf_counter() - t0, 2)))
 
-    def reroute(self, cost_s, off, edges, n):
+    def reroute(self, cost_s, off, edges, n, out=None):
+        """Routes of MSA iteration n (1-based) on edge costs cost_s: the new
+        shortest routes for the trips the switch picks, the old routes for
+        the rest; `out` as in Router.routes."""
         t0 = time.perf_counter()
         take = msa_switch(len(self.origin), n, self.seed)
         new = self.router.routes(cost_s, self.origin, self.dest, old=(off, edges), take_new=take,
-                                 timings=self.timings)
+                                 timings=self.timings, out=out)
         self._add("route", time.perf_counter() - t0)
+        return new
+
+    def _new_route_buffers(self):
+        # two route buffers used in turn by the MSA loops, which hold only
+        # the current and the previous routes: one iteration's routes are
+        # written while the other buffer holds the previous ones.  Each run
+        # starts with new ones, so routes a run returned are never
+        # overwritten.
+        self._route_buf = [None, None]
+        self._route_k = 0
+
+    def _reroute_in_turn(self, cost_s, off, edges, n):
+        k = self._route_k
+        buf = self._route_buf[k]
+        new = self.reroute(cost_s, off, edges, n, out=buf if buf is not None else np.empty(0, np.int32))
+        self._route_buf[k] = new[1].base if new[1].base is not None else new[1]
+        self._route_k = k ^ 1
         return new
 
     # -- plain MSA -------------------------------------------------------------
     def run_plain(self, n_iter):
+        self._new_route_buffers()
         t0 = time.perf_counter()
         off, edges = self.inst.route_off, self.inst.route_edges
         hist = []
@@ -184,7 +215,7 @@ class Assignment:
             tt = self.edge_tt_from_stats(st)
             hist.append({"n": n, "mode": "sim", "mean_tt": float(np.average(tt, weights=st["n_exits"] + 1e-9))})
             self._progress(hist[-1], t0)
-            off, edges = self.reroute(tt, off, edges, n)
+            off, edges = self._reroute_in_turn(tt, off, edges, n)
         wall = time.perf_counter() - t0
         st = self.simulate(off, edges, binned=False)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,
@@ -331,6 +362,7 @@ class Assignment:
         torch = self.torch
         dev = "cuda"
         net = EdgeMLP(seed=mlp_seed)
+        self._new_route_buffers()
         t0 = time.perf_counter()
         off, edges = self.inst.route_off, self.inst.route_edges
         hist = []
@@ -390,7 +422,7 @@ class Assignment:
                 self._add("surrogate", time.perf_counter() - ts)
                 hist.append({"n": n, "mode": "surrogate"})
                 self._progress(hist[-1], t0)
-            off, edges = self.reroute(tt, off, edges, n)
+            off, edges = self._reroute_in_turn(tt, off, edges, n)
         wall = time.perf_counter() - t0
         st = self.simulate(off, edges, binned=False)
         return {"wall_s": wall, "tt": self.edge_tt_from_stats(st), "exits": st["n_exits"], "hist": hist,

@@ -29,8 +29,9 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
                          const int32_t *in_edges_h, const int32_t *in_src_h, const int32_t *src_h,
                          const int32_t *dst_h, const double *cost_h, const int32_t *dests, int32_t nd,
                          int64_t n_trips, const int32_t *origin_h, const int32_t *dest_idx_h, hipStream_t s);
-int32_t gpu_router_routes(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, const int64_t *new_off,
-                          int32_t *new_edges, hipStream_t s);
+int32_t gpu_router_lengths(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, hipStream_t s);
+int64_t *gpu_router_offsets(GpuRouter *g);
+int32_t gpu_router_write(GpuRouter *g, const int32_t **packed, hipStream_t s);
 }  // namespace lpsim_route
 
 struct lpsim_router {
@@ -50,6 +51,10 @@ struct lpsim_router {
     bool on_gpu = false;         // the last solve ran on the GPU
     void *gpu_stream = nullptr;  // and on this stream
     std::vector<int32_t> len;        // per trip, new route length (trips taking one)
+    // lengths in len are those of the trips chosen by len_take (all trips if
+    // len_all) for the last solve
+    bool len_ok = false, len_all = false;
+    std::vector<uint8_t> len_take;
     bool solved = false;
     lpsim_route::GpuRouter *gpu = nullptr;  // device copy of the graph (GPU solves)
 };
@@ -112,6 +117,29 @@ void parallel_for(int32_t n_items, int32_t n_threads, F &&f) {
     for (auto &t : pool) t.join();
 }
 
+// out[0] = 0, out[i + 1] = out[i] + len_of(i) for i < n: chunk sums on the
+// router's threads, their running total, then every chunk from its start
+template <class F>
+void prefix_sum(int64_t n, int32_t n_threads, int64_t *out, F &&len_of) {
+    const int64_t chunk = 65536;
+    const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
+    std::vector<int64_t> start((size_t)n_chunks + 1, 0);
+    parallel_for(n_chunks, n_threads, [&](int32_t ci) {
+        int64_t s = 0;
+        for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) s += len_of(i);
+        start[(size_t)ci + 1] = s;
+    });
+    for (int32_t ci = 0; ci < n_chunks; ++ci) start[(size_t)ci + 1] += start[(size_t)ci];
+    out[0] = 0;
+    parallel_for(n_chunks, n_threads, [&](int32_t ci) {
+        int64_t s = start[(size_t)ci];
+        for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
+            s += len_of(i);
+            out[i + 1] = s;
+        }
+    });
+}
+
 }  // namespace
 
 extern "C" {
@@ -160,6 +188,7 @@ static int32_t router_solve(lpsim_router *r, const double *cost, int64_t n_trips
     for (int32_t e = 0; e < r->n_edges; ++e)
         if (!(cost[e] > 0.0) || !std::isfinite(cost[e])) return LPSIM_EINVAL;
     r->solved = false;
+    r->len_ok = false;
     try {
         // distinct destinations in order of first appearance
         std::vector<int32_t> idx((size_t)r->n_nodes, -1);
@@ -283,24 +312,36 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
     const int64_t chunk = 65536;
     const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
     if (r->on_gpu) {
-        // lengths of the new routes from walks on the device (every call, as
-        // below); with out_edges, the new routes come back packed and the
-        // old ones are copied on the host
-        const int32_t rc = lpsim_route::gpu_router_routes(r->gpu, take_new, r->len.data(), nullptr, nullptr,
-                                                          (hipStream_t)r->gpu_stream);
-        if (rc) return rc;
-        out_off[0] = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            const bool nw = !take_new || take_new[i];
-            out_off[i + 1] = out_off[i] + (nw ? r->len[(size_t)i] : old_off[i + 1] - old_off[i]);
+        // lengths of the new routes from walks on the device; a call that
+        // follows a sizing call for the same choice of trips reuses them
+        const bool same = r->len_ok && (take_new ? !r->len_all && r->len_take.size() == (size_t)n &&
+                                                       std::memcmp(r->len_take.data(), take_new, (size_t)n) == 0
+                                                 : r->len_all);
+        if (!same) {
+            r->len_ok = false;
+            const int32_t rc = lpsim_route::gpu_router_lengths(r->gpu, take_new, r->len.data(),
+                                                               (hipStream_t)r->gpu_stream);
+            if (rc) return rc;
+            try {
+                if (take_new) r->len_take.assign(take_new, take_new + n);
+            } catch (...) {
+                return LPSIM_ENOMEM;
+            }
+            r->len_all = !take_new;
+            r->len_ok = true;
         }
+        const int32_t *len = r->len.data();
+        prefix_sum(n, r->n_threads, out_off, [&](int64_t i) -> int64_t {
+            return !take_new || take_new[i] ? len[i] : old_off[i + 1] - old_off[i];
+        });
         if (!out_edges) return LPSIM_OK;
-        std::vector<int64_t> poff((size_t)n + 1);
-        poff[0] = 0;
-        for (int64_t i = 0; i < n; ++i) poff[(size_t)i + 1] = poff[(size_t)i] + r->len[(size_t)i];
-        std::vector<int32_t> packed((size_t)std::max<int64_t>(poff[(size_t)n], 1));
-        const int32_t rc2 = lpsim_route::gpu_router_routes(r->gpu, take_new, r->len.data(), poff.data(),
-                                                           packed.data(), (hipStream_t)r->gpu_stream);
+        // the new routes come back packed (page-locked), the old ones are
+        // copied on the host
+        int64_t *poff = lpsim_route::gpu_router_offsets(r->gpu);
+        if (!poff) return LPSIM_ENOMEM;
+        prefix_sum(n, r->n_threads, poff, [&](int64_t i) -> int64_t { return len[i]; });
+        const int32_t *packed = nullptr;
+        const int32_t rc2 = lpsim_route::gpu_router_write(r->gpu, &packed, (hipStream_t)r->gpu_stream);
         if (rc2) return rc2;
         parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
             for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
@@ -308,7 +349,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
                 if (take_new && !take_new[i])
                     std::memcpy(o, old_edges + old_off[i], (size_t)(old_off[i + 1] - old_off[i]) * 4);
                 else
-                    std::memcpy(o, packed.data() + poff[(size_t)i], (size_t)r->len[(size_t)i] * 4);
+                    std::memcpy(o, packed + poff[i], (size_t)len[i] * 4);
             }
         });
         return LPSIM_OK;
@@ -331,11 +372,11 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
             }
         });
     }
-    out_off[0] = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const bool nw = !take_new || take_new[i];
-        const int64_t l = nw ? r->len[(size_t)i] : old_off[i + 1] - old_off[i];
-        out_off[i + 1] = out_off[i] + l;
+    {
+        const int32_t *len = r->len.data();
+        prefix_sum(n, r->n_threads, out_off, [&](int64_t i) -> int64_t {
+            return !take_new || take_new[i] ? len[i] : old_off[i + 1] - old_off[i];
+        });
     }
     if (!out_edges) return LPSIM_OK;
     parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {

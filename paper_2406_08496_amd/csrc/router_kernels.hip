@@ -38,6 +38,21 @@ constexpr int THREADS = 256;
 constexpr int GRID = 2048;         // blocks of the grid-stride kernels
 constexpr int PUSH_BUF = 4 * THREADS;  // per-block staging of queued pairs
 constexpr double DELTA_COSTS = 16.0;    // near-far threshold step, in mean edge costs
+constexpr int32_t ROUNDS_AHEAD = 16;    // first group of rounds launched between reads of the state
+
+// Round state of one destination batch's relaxation, on the device: a
+// one-thread kernel after each round takes the step between rounds, so the
+// host launches rounds ahead and only reads `done` every few rounds.
+struct RoundCtl {
+    uint32_t count[3];             // near frontier sizes, by round mod 3
+    uint32_t far_count[2];         // the two far piles
+    uint32_t done;                 // both frontiers empty
+    uint32_t split;                // the pile was split after round `round`: the
+                                   // next round is round + 1 with the piles switched
+    int32_t round, fc;             // round number, far pile being filled
+    unsigned long long far_min;    // least distance bits entering the pile
+    double tau, delta;             // threshold and its step
+};
 
 struct GpuRouter {
     int32_t n = 0, m = 0;
@@ -51,7 +66,8 @@ struct GpuRouter {
     unsigned long long *dist = nullptr;
     uint2 *front[2] = {nullptr, nullptr};
     uint32_t *flags[2] = {nullptr, nullptr};  // one bit per pair
-    uint32_t *count = nullptr;                // [3] frontier sizes, by round mod 3
+    RoundCtl *ctl = nullptr;
+    uint32_t *count = nullptr;                // ctl->count
     int32_t *targets = nullptr;
     // tree edge of every (destination, node) of the last solve
     int32_t *nx = nullptr;
@@ -66,12 +82,20 @@ struct GpuRouter {
     int64_t *poff = nullptr;       // [n_trips + 1] offsets of the packed new routes
     int32_t *packed = nullptr;     // the new routes, packed
     size_t packed_cap = 0;
+    bool take_all = true;          // the last length walk took every trip
+    // page-locked host copies of the offsets and of the packed routes, kept
+    // across calls (fast transfers, no fresh pages per call)
+    int64_t *poff_h = nullptr;
+    size_t poff_h_cap = 0;
+    RoundCtl *ctl_h = nullptr;     // page-locked copy of ctl read between groups of rounds
+    int32_t *packed_h = nullptr;
+    size_t packed_h_cap = 0;
     uint32_t *bad = nullptr;       // a trip whose destination cannot be reached
     // far pile: pairs whose distance dropped above the threshold
     uint2 *far[2] = {nullptr, nullptr};
     uint32_t *far_flags = nullptr;             // one bit per pair in the pile
-    uint32_t *far_count = nullptr;             // [2]
-    unsigned long long *far_min = nullptr;     // least distance bits entering the pile
+    uint32_t *far_count = nullptr;             // ctl->far_count
+    unsigned long long *far_min = nullptr;     // &ctl->far_min
     std::vector<void *> allocs;
 };
 
@@ -95,7 +119,7 @@ __global__ void k_init(GpuRouter g, int32_t nd) {
     }
 }
 
-__global__ void k_seed(GpuRouter g, int32_t nd) {
+__global__ void k_seed(GpuRouter g, int32_t nd, double delta) {
     for (int32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
         const size_t pair = (size_t)d * g.n + (size_t)g.targets[d];
         g.dist[pair] = 0ull;
@@ -109,6 +133,12 @@ __global__ void k_seed(GpuRouter g, int32_t nd) {
         g.far_count[0] = 0;
         g.far_count[1] = 0;
         *g.far_min = ~0ull;
+        g.ctl->done = 0;
+        g.ctl->split = 0;
+        g.ctl->round = 0;
+        g.ctl->fc = 0;
+        g.ctl->tau = delta;
+        g.ctl->delta = delta;
     }
 }
 
@@ -143,10 +173,15 @@ __device__ __forceinline__ void block_min(unsigned long long v, unsigned long lo
 // other near frontier, a drop above tau puts it (once) in the far pile.  A
 // processed pair's queue flag is cleared here (nothing queues into this
 // round's frontier during the round), and the size counter of round r + 2 is
-// reset (round r - 1, its last reader, has finished).
-__global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t round, double tau, int32_t fc) {
+// reset (round r - 1, its last reader, has finished).  Nothing runs once the
+// batch is done (the host launches rounds ahead).
+__global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g) {
     __shared__ PushBuf bn, bf;
     __shared__ unsigned long long s_min;
+    const RoundCtl *const c = g.ctl;
+    if (c->done) return;
+    const int32_t round = c->round + (int32_t)c->split, fc = c->fc ^ (int32_t)c->split;
+    const double tau = c->tau;
     const int32_t cur = round & 1;
     const uint32_t nf = g.count[round % 3];
     const uint2 *front = g.front[cur];
@@ -202,12 +237,44 @@ __global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g, int32_t round, d
     }
 }
 
+// the step between rounds, after round r: with the next near frontier empty
+// the batch is done if the pile is empty too; else tau moves up by delta, or
+// at once to the nearest waiting pair, and the pile is split (k_split) before
+// round r + 1
+__global__ void k_round_ctl(GpuRouter g) {
+    RoundCtl *const c = g.ctl;
+    if (c->done) return;
+    if (c->split) {  // the round that just ran followed a split
+        c->round += 1;
+        c->fc ^= 1;
+        c->split = 0;
+    }
+    const int32_t round = c->round, fc = c->fc;
+    if (c->count[(round + 1) % 3] != 0) {
+        c->round = round + 1;
+    } else if (c->far_count[fc] == 0) {
+        c->done = 1;
+    } else {
+        const double fmin = __longlong_as_double((long long)c->far_min);
+        const double up = c->tau + c->delta;
+        c->tau = up < fmin ? fmin : up;
+        c->far_count[fc ^ 1] = 0;
+        c->far_min = ~0ull;
+        c->split = 1;
+    }
+}
+
 // the near frontier ran dry: the far pile (buffer fc) is split by the new
 // threshold tau; pairs now within it join the next near frontier (round r +
-// 1), the others move to pile fc ^ 1, whose least distance is recorded
-__global__ __launch_bounds__(THREADS) void k_split(GpuRouter g, int32_t round, double tau, int32_t fc) {
+// 1), the others move to pile fc ^ 1, whose least distance is recorded.
+// Launched after every round, it does nothing unless k_round_ctl asked for it.
+__global__ __launch_bounds__(THREADS) void k_split(GpuRouter g) {
     __shared__ PushBuf bn, bf;
     __shared__ unsigned long long s_min;
+    const RoundCtl *const c = g.ctl;
+    if (c->done || !c->split) return;
+    const int32_t round = c->round, fc = c->fc;
+    const double tau = c->tau;
     const int32_t nxt = (round + 1) & 1;
     uint2 *next = g.front[nxt];
     uint32_t *nflags = g.flags[nxt];
@@ -326,6 +393,9 @@ static hipError_t alloc(GpuRouter *g, T *&p, size_t n) {
 void gpu_router_free(GpuRouter *g) {
     if (!g) return;
     for (void *p : g->allocs) (void)hipFree(p);
+    if (g->poff_h) (void)hipHostFree(g->poff_h);
+    if (g->ctl_h) (void)hipHostFree(g->ctl_h);
+    if (g->packed_h) (void)hipHostFree(g->packed_h);
     delete g;
 }
 
@@ -370,9 +440,11 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         RCHK(alloc(g, g->in_cost, (size_t)n_edges));
         RCHK(alloc(g, g->out_cost, (size_t)n_edges));
         RCHK(alloc(g, g->cost, (size_t)n_edges));
-        RCHK(alloc(g, g->count, 3));
-        RCHK(alloc(g, g->far_count, 2));
-        RCHK(alloc(g, g->far_min, 1));
+        RCHK(alloc(g, g->ctl, 1));
+        g->count = g->ctl->count;
+        g->far_count = g->ctl->far_count;
+        g->far_min = &g->ctl->far_min;
+        RCHK(hipHostMalloc((void **)&g->ctl_h, sizeof(RoundCtl), hipHostMallocDefault));
         RCHK(alloc(g, g->bad, 1));
         RCHK(alloc(g, g->edge_dst, (size_t)n_edges));
         RCHK(hipMemcpy(g->edge_dst, dst_h, (size_t)n_edges * 4, hipMemcpyHostToDevice));
@@ -434,45 +506,26 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
         const int32_t nb = std::min(per, nd - d0);
         RCHK(hipMemcpyAsync(g->targets, dests + d0, (size_t)nb * 4, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_init, dim3(GRID), dim3(THREADS), 0, s, *g, nb);
-        hipLaunchKernelGGL(k_seed, dim3((nb + THREADS - 1) / THREADS), dim3(THREADS), 0, s, *g, nb);
+        hipLaunchKernelGGL(k_seed, dim3((nb + THREADS - 1) / THREADS), dim3(THREADS), 0, s, *g, nb, delta);
         RCHK(hipGetLastError());
-        // rounds until the near frontier and the far pile are both empty;
-        // the host reads the sizes after every round and moves the threshold
-        int32_t round = 0, fc = 0;
-        double tau = delta;
-        // each round settles at least one more hop of every shortest path
-        // within the threshold, and the threshold only rises; past this bound
-        // something is wrong (it cannot happen with finite positive costs)
+        // rounds until the near frontier and the far pile are both empty,
+        // launched ahead in groups; the host reads the state between groups
+        // (rounds after the last one return at once).  Each round settles at
+        // least one more hop of every shortest path within the threshold,
+        // and the threshold only rises; past this bound something is wrong
+        // (it cannot happen with finite positive costs)
         const int64_t max_rounds = 4ll * n_nodes + 1024;
-        for (int64_t rounds = 0;; ++rounds) {
-            if (rounds > max_rounds) return LPSIM_EDEVICE;
-            hipLaunchKernelGGL(k_relax, dim3(GRID), dim3(THREADS), 0, s, *g, round, tau, fc);
-            RCHK(hipGetLastError());
-            struct {
-                uint32_t count[3], far_count[2];
-                unsigned long long far_min;
-            } st;
-            RCHK(hipMemcpyAsync(st.count, g->count, sizeof st.count, hipMemcpyDeviceToHost, s));
-            RCHK(hipMemcpyAsync(st.far_count, g->far_count, sizeof st.far_count, hipMemcpyDeviceToHost, s));
-            RCHK(hipMemcpyAsync(&st.far_min, g->far_min, 8, hipMemcpyDeviceToHost, s));
-            RCHK(hipStreamSynchronize(s));
-            if (st.count[(round + 1) % 3] == 0) {
-                if (st.far_count[fc] == 0) break;
-                // next threshold: one step up, or at once to the nearest
-                // waiting pair; the pile is split into the near frontier and
-                // the other pile
-                double fmin;
-                std::memcpy(&fmin, &st.far_min, 8);
-                tau = std::max(tau + delta, fmin);
-                const uint32_t zero = 0;
-                const unsigned long long inf = ~0ull;
-                RCHK(hipMemcpyAsync(&g->far_count[fc ^ 1], &zero, 4, hipMemcpyHostToDevice, s));
-                RCHK(hipMemcpyAsync(g->far_min, &inf, 8, hipMemcpyHostToDevice, s));
-                hipLaunchKernelGGL(k_split, dim3(GRID), dim3(THREADS), 0, s, *g, round, tau, fc);
-                RCHK(hipGetLastError());
-                fc ^= 1;
+        for (int32_t group = ROUNDS_AHEAD;; group = std::min(2 * group, 4 * ROUNDS_AHEAD)) {
+            for (int32_t k = 0; k < group; ++k) {
+                hipLaunchKernelGGL(k_relax, dim3(GRID), dim3(THREADS), 0, s, *g);
+                hipLaunchKernelGGL(k_round_ctl, dim3(1), dim3(1), 0, s, *g);
+                hipLaunchKernelGGL(k_split, dim3(GRID), dim3(THREADS), 0, s, *g);
             }
-            ++round;
+            RCHK(hipGetLastError());
+            RCHK(hipMemcpyAsync(g->ctl_h, g->ctl, sizeof(RoundCtl), hipMemcpyDeviceToHost, s));
+            RCHK(hipStreamSynchronize(s));
+            if (g->ctl_h->done) break;
+            if (g->ctl_h->round > max_rounds) return LPSIM_EDEVICE;
         }
         hipLaunchKernelGGL(k_ties, dim3(GRID), dim3(THREADS), 0, s, *g, nb, d0);
         RCHK(hipGetLastError());
@@ -487,33 +540,70 @@ int32_t gpu_router_solve(GpuRouter **gp, int32_t n_nodes, int32_t n_edges, const
     return bad ? LPSIM_EINVAL : LPSIM_OK;
 }
 
-// Routes of the last GPU solve: new_len (host, n_trips) receives the length
-// of each new route (0 where take[i] == 0; take NULL takes all).  With
-// new_edges (host) and new_off (host, n_trips + 1 offsets of the packed new
-// routes, from new_len) the new routes are written there, packed.
-int32_t gpu_router_routes(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, const int64_t *new_off,
-                          int32_t *new_edges, hipStream_t s) {
+// Lengths of the new routes of the last GPU solve: new_len (host, n_trips)
+// receives the length of each new route (0 where take[i] == 0; take NULL
+// takes all).  The choice stays on the device for gpu_router_write.
+int32_t gpu_router_lengths(GpuRouter *g, const uint8_t *take_h, int32_t *new_len, hipStream_t s) {
     if (!g) return LPSIM_ESTATE;
     const int64_t n = g->n_trips;
     if (take_h) RCHK(hipMemcpyAsync(g->take, take_h, (size_t)n, hipMemcpyHostToDevice, s));
+    g->take_all = take_h == nullptr;
     GpuRouter gv = *g;
-    if (!take_h) gv.take = nullptr;
-    if (!new_edges) {
-        hipLaunchKernelGGL(k_walk_len, dim3(GRID), dim3(THREADS), 0, s, gv);
-        RCHK(hipGetLastError());
-        RCHK(hipMemcpyAsync(new_len, g->len, (size_t)n * 4, hipMemcpyDeviceToHost, s));
-        return status(hipStreamSynchronize(s));
+    if (g->take_all) gv.take = nullptr;
+    hipLaunchKernelGGL(k_walk_len, dim3(GRID), dim3(THREADS), 0, s, gv);
+    RCHK(hipGetLastError());
+    RCHK(hipMemcpyAsync(new_len, g->len, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    return status(hipStreamSynchronize(s));
+}
+
+// Page-locked host buffer of n_trips + 1 offsets for gpu_router_write (NULL
+// if it cannot be allocated); the caller fills it with the exclusive prefix
+// of the lengths from gpu_router_lengths.
+int64_t *gpu_router_offsets(GpuRouter *g) {
+    if (!g) return nullptr;
+    const size_t need = (size_t)g->n_trips + 1;
+    if (g->poff_h_cap < need) {
+        if (g->poff_h) (void)hipHostFree(g->poff_h);
+        g->poff_h = nullptr;
+        g->poff_h_cap = 0;
+        if (hipHostMalloc((void **)&g->poff_h, need * 8, hipHostMallocDefault) != hipSuccess) {
+            g->poff_h = nullptr;
+            return nullptr;
+        }
+        g->poff_h_cap = need;
     }
-    const size_t total = (size_t)new_off[n];
+    return g->poff_h;
+}
+
+// The new routes of the trips chosen by the last gpu_router_lengths, walked
+// on the device and copied back packed at the offsets in gpu_router_offsets'
+// buffer; *packed points at them (page-locked, valid until the next call).
+int32_t gpu_router_write(GpuRouter *g, const int32_t **packed, hipStream_t s) {
+    if (!g || !g->poff_h) return LPSIM_ESTATE;
+    const int64_t n = g->n_trips;
+    const size_t total = (size_t)g->poff_h[n];
     if (g->packed_cap < total) {
         RCHK(alloc(g, g->packed, total));
         g->packed_cap = total;
     }
-    gv.packed = g->packed;
-    RCHK(hipMemcpyAsync(g->poff, new_off, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
+    if (g->packed_h_cap < std::max<size_t>(total, 1)) {
+        if (g->packed_h) (void)hipHostFree(g->packed_h);
+        g->packed_h = nullptr;
+        g->packed_h_cap = 0;
+        const size_t cap = std::max<size_t>(total, 1);
+        if (hipHostMalloc((void **)&g->packed_h, cap * 4, hipHostMallocDefault) != hipSuccess) {
+            g->packed_h = nullptr;
+            return LPSIM_ENOMEM;
+        }
+        g->packed_h_cap = cap;
+    }
+    GpuRouter gv = *g;
+    if (g->take_all) gv.take = nullptr;
+    RCHK(hipMemcpyAsync(g->poff, g->poff_h, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_walk_write, dim3(GRID), dim3(THREADS), 0, s, gv);
     RCHK(hipGetLastError());
-    if (total) RCHK(hipMemcpyAsync(new_edges, g->packed, total * 4, hipMemcpyDeviceToHost, s));
+    if (total) RCHK(hipMemcpyAsync(g->packed_h, g->packed, total * 4, hipMemcpyDeviceToHost, s));
+    *packed = g->packed_h;
     return status(hipStreamSynchronize(s));
 }
 

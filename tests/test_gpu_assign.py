@@ -154,6 +154,13 @@ def test_msa_small_end_to_end(torch):
             assert np.all(inst.dst[r[:-1]] == inst.src[r[1:]])
     g = agreement(sur["tt"], plain["tt"], plain["exits"])
     assert np.isfinite(g)
+    # the loops write routes into two buffers in turn; a second run on the
+    # same object leaves the routes the first one returned untouched, and
+    # the same routes come out again
+    keep = (plain["routes"][0].copy(), plain["routes"][1].copy())
+    again = a.run_plain(6)
+    assert np.array_equal(plain["routes"][0], keep[0]) and np.array_equal(plain["routes"][1], keep[1])
+    assert np.array_equal(again["routes"][0], keep[0]) and np.array_equal(again["routes"][1], keep[1])
 
 
 def test_trained_network_gain(torch):

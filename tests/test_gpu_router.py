@@ -4,6 +4,8 @@ trip and edge by edge, on grids and planar graphs, with free-flow costs,
 random costs and integer costs full of ties, at the size of the regional
 workload's 500 destinations; and route costs equal to an independent
 Dijkstra (scipy) where the check applies."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -80,3 +82,58 @@ def test_gpu_unreachable_is_an_error(torch):
         r.routes(np.array([1.0, 2.0]), np.array([2], np.int32), np.array([0], np.int32))
     off, edges = r.routes(np.array([1.0, 2.0]), np.array([0], np.int32), np.array([2], np.int32))
     assert list(edges) == [0, 1]
+
+
+def test_gpu_router_reused_across_solves(torch):
+    """One router solved again and again (new costs, a shrinking then growing
+    share of trips moved, routes chained from the last call) gives the host
+    router's routes every time; a fill whose choice of trips differs from
+    the sizing call's before it measures its own lengths."""
+    from paper_2406_08496_amd.assign import _p, msa_switch
+
+    inst = synth.grid_instance(seed=8, side=11, n_trips=3000)
+    rng = np.random.default_rng(5)
+    base = inst.length.astype(np.float64) / inst.speed.astype(np.float64)
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    host = Router(inst.n_nodes, inst.src, inst.dst, n_threads=4)
+    gpu = Router(inst.n_nodes, inst.src, inst.dst, gpu=True)
+    old = (inst.route_off, inst.route_edges)
+    for it, n in enumerate((1, 7, 2, None)):
+        cost = base * rng.uniform(0.5, 3.0, size=inst.n_edges)
+        take = None if n is None else msa_switch(len(o), n, 0x77)
+        case("reused GPU router, solve", it, "take share", "all" if n is None else f"1/{n + 1}")
+        a = host.routes(cost, o, d, old=old, take_new=take)
+        b = gpu.routes(cost, o, d, old=old, take_new=take)
+        assert_same_routes(a, b, f"solve {it}")
+        old = b
+    # sizing with one choice, edges with another
+    cost = base * rng.uniform(0.5, 3.0, size=inst.n_edges)
+    t1 = msa_switch(len(o), 3, 0x99)
+    t2 = msa_switch(len(o), 4, 0x99)
+    assert not np.array_equal(t1, t2)
+    want = host.routes(cost, o, d, old=old, take_new=t2)
+    gpu.routes(cost, o, d, old=old, take_new=t2)  # solve on the device for this cost
+    oo = np.ascontiguousarray(old[0], np.int64)
+    oe = np.ascontiguousarray(old[1], np.int32)
+    off1 = np.empty(len(o) + 1, np.int64)
+    assert gpu.lib.lpsim_router_fill(gpu._h, _p(oo), _p(oe), _p(t1), _p(off1), None) == 0
+    off2 = np.empty(len(o) + 1, np.int64)
+    assert gpu.lib.lpsim_router_fill(gpu._h, _p(oo), _p(oe), _p(t2), _p(off2), None) == 0
+    assert gpu.lib.lpsim_router_fill(gpu._h, _p(oo), _p(oe), _p(t1), _p(off1), None) == 0
+    edges = np.full(int(off2[-1]) + 16, -7, np.int32)
+    case("fill after a sizing call for another choice of trips")
+    assert gpu.lib.lpsim_router_fill(gpu._h, _p(oo), _p(oe), _p(t2), _p(off2), _p(edges)) == 0
+    assert np.array_equal(off2, want[0])
+    assert np.array_equal(edges[:off2[-1]], want[1])
+    assert (edges[off2[-1]:] == -7).all()
+    # a solve, then the edges written without a sizing call
+    c = np.ascontiguousarray(cost)
+    oi = np.ascontiguousarray(o, np.int32)
+    di = np.ascontiguousarray(d, np.int32)
+    assert gpu.lib.lpsim_router_solve_gpu(gpu._h, _p(c), len(o), _p(oi), _p(di),
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+    off3 = np.empty(len(o) + 1, np.int64)
+    edges3 = np.empty(int(off2[-1]), np.int32)
+    case("fill of the edges without a sizing call")
+    assert gpu.lib.lpsim_router_fill(gpu._h, _p(oo), _p(oe), _p(t2), _p(off3), _p(edges3)) == 0
+    assert np.array_equal(off3, want[0]) and np.array_equal(edges3, want[1])

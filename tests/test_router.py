@@ -121,6 +121,35 @@ def test_fill_in_one_call():
     assert np.array_equal(off1, off2) and np.array_equal(edges1, edges2)
 
 
+def test_routes_into_a_reused_buffer():
+    """routes(out=...) writes into the caller's buffer when it is large
+    enough and is not the old routes' memory, else into a new array with
+    room to spare; the routes are the same either way."""
+    inst = synth.grid_instance(seed=7, side=6, n_trips=300)
+    cost = (inst.length / inst.speed).astype(np.float64) * np.linspace(1.0, 2.0, inst.n_edges)
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=2)
+    take = (np.arange(inst.n_trips) % 2 == 0).astype(np.uint8)
+    old = (inst.route_off, inst.route_edges)
+    want = r.routes(cost, o, d, old=old, take_new=take)
+    # too small: a new array with room, whose base can be reused
+    a = r.routes(cost, o, d, old=old, take_new=take, out=np.empty(0, np.int32))
+    assert np.array_equal(a[0], want[0]) and np.array_equal(a[1], want[1])
+    buf = a[1].base
+    assert buf is not None and len(buf) > len(a[1])
+    buf[:] = -5
+    b = r.routes(cost, o, d, old=old, take_new=take, out=buf)
+    assert np.shares_memory(b[1], buf)
+    assert np.array_equal(b[0], want[0]) and np.array_equal(b[1], want[1])
+    assert (buf[len(b[1]):] == -5).all()
+    # the old routes' own memory is never written
+    old2 = (b[0], b[1])
+    c = r.routes(cost * 1.3, o, d, old=old2, take_new=take, out=buf)
+    assert not np.shares_memory(c[1], buf)
+    c_want = r.routes(cost * 1.3, o, d, old=(b[0].copy(), b[1].copy()), take_new=take)
+    assert np.array_equal(c[0], c_want[0]) and np.array_equal(c[1], c_want[1])
+
+
 def test_msa_switch_definition():
     """lpsim_msa_switch against its definition written out with Python
     integers: SplitMix64 of seed ^ i << 8 ^ n, modulo n + 1."""
