@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--mlp-only", action="store_true", help="only run the surrogate perceptron leg")
     ap.add_argument("--mlp-samples", type=int, default=2_200_000,
                     help="inference batch of the perceptron leg (550k edges x 4 one-hour windows)")
+    ap.add_argument("--route-only", type=int, default=0, metavar="N",
+                    help="only time the routing step of N MSA iterations on the regional network "
+                         "(GPU trees toward its 500 destinations, new routes for the switched trips)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM traffic counters")
     ap.add_argument("--summarize-profile", default=None, metavar="CSV",
@@ -276,6 +279,9 @@ def main():
         return
     if args.mlp_only:
         print(json.dumps({"surrogate_mlp": run_mlp(args.mlp_samples, 8192)}), flush=True)
+        return
+    if args.route_only:
+        print(json.dumps({"routing": run_routing(args.route_only)}), flush=True)
         return
     t = time.perf_counter()
     inst, n_bins = make_workload(args.workload)
@@ -521,6 +527,42 @@ def run_mlp(n_fwd, n_train, reps=10):
         out[name] = dict(entry(MLP_BWD_FLOP * n, timed(lambda: net.backward(xb, hs, dz))), samples=n)
         del y, hs, dz, tgt, xb
     return out
+
+
+def run_routing(n_iter, seed=11):
+    """The routing step of MSA iterations 1..n_iter on the regional network,
+    on its own: edge costs are the free-flow times times a seeded log-normal
+    congestion factor (a new draw each iteration), the switch moves 1/(n+1)
+    of the trips, and each iteration's routes start from the last ones, as
+    in the loop.  Host wall clock per iteration: the tree solve and writing
+    the routes."""
+    from paper_2406_08496_amd import synth
+    from paper_2406_08496_amd.assign import Router, msa_switch
+
+    inst = synth.regional()
+    rng = np.random.default_rng(seed)
+    base = inst.length.astype(np.float64) / inst.speed.astype(np.float64)
+    o = np.ascontiguousarray(inst.meta["origin"], np.int32)
+    d = np.ascontiguousarray(inst.meta["dest"], np.int32)
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=16, gpu=True)
+    old = (inst.route_off, inst.route_edges)
+    bufs = [np.empty(0, np.int32), np.empty(0, np.int32)]
+    rows = []
+    for n in range(1, n_iter + 1):
+        cost = base * np.exp(rng.normal(0.0, 0.5, inst.n_edges))
+        take = msa_switch(len(o), n, 0xA55)
+        tm = {}
+        new = r.routes(cost, o, d, old=old, take_new=take, timings=tm, out=bufs[n % 2])
+        bufs[n % 2] = new[1].base if new[1].base is not None else new[1]
+        rows.append({"n": n, "solve_ms": round(tm["route_solve"] * 1e3, 2), "fill_ms": round(tm["route_fill"] * 1e3, 2),
+                     "moved": int(take.sum()), "route_entries": int(new[0][-1])})
+        log("routing", json.dumps(rows[-1]))
+        old = new
+    later = rows[1:] or rows
+    return {"workload": inst.name, "trips": len(o), "destinations": int(len(np.unique(d))),
+            "iterations": rows,
+            "mean_after_first_ms": {"solve": round(float(np.mean([x["solve_ms"] for x in later])), 2),
+                                    "fill": round(float(np.mean([x["fill_ms"] for x in later])), 2)}}
 
 
 def run_assignment(inst, n_iter):

@@ -179,9 +179,10 @@ __global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g) {
     __shared__ PushBuf bn, bf;
     __shared__ unsigned long long s_min;
     const RoundCtl *const c = g.ctl;
-    if (c->done) return;
-    const int32_t round = c->round + (int32_t)c->split, fc = c->fc ^ (int32_t)c->split;
+    const uint32_t done = c->done, split = c->split;
+    const int32_t round = c->round + (int32_t)split, fc = c->fc ^ (int32_t)split;
     const double tau = c->tau;
+    if (done) return;
     const int32_t cur = round & 1;
     const uint32_t nf = g.count[round % 3];
     const uint2 *front = g.front[cur];
@@ -243,20 +244,21 @@ __global__ __launch_bounds__(THREADS) void k_relax(GpuRouter g) {
 // round r + 1
 __global__ void k_round_ctl(GpuRouter g) {
     RoundCtl *const c = g.ctl;
-    if (c->done) return;
-    if (c->split) {  // the round that just ran followed a split
-        c->round += 1;
-        c->fc ^= 1;
-        c->split = 0;
-    }
-    const int32_t round = c->round, fc = c->fc;
-    if (c->count[(round + 1) % 3] != 0) {
+    const RoundCtl v = *c;  // the whole block in one round trip
+    if (v.done) return;
+    // the round that just ran followed a split if one is pending
+    const int32_t round = v.round + (int32_t)v.split, fc = v.fc ^ (int32_t)v.split;
+    c->fc = fc;
+    c->split = 0;
+    if (v.count[(round + 1) % 3] != 0) {
         c->round = round + 1;
-    } else if (c->far_count[fc] == 0) {
+    } else if (v.far_count[fc] == 0) {
+        c->round = round;
         c->done = 1;
     } else {
-        const double fmin = __longlong_as_double((long long)c->far_min);
-        const double up = c->tau + c->delta;
+        const double fmin = __longlong_as_double((long long)v.far_min);
+        const double up = v.tau + v.delta;
+        c->round = round;
         c->tau = up < fmin ? fmin : up;
         c->far_count[fc ^ 1] = 0;
         c->far_min = ~0ull;
@@ -272,9 +274,10 @@ __global__ __launch_bounds__(THREADS) void k_split(GpuRouter g) {
     __shared__ PushBuf bn, bf;
     __shared__ unsigned long long s_min;
     const RoundCtl *const c = g.ctl;
-    if (c->done || !c->split) return;
+    const uint32_t done = c->done, split = c->split;
     const int32_t round = c->round, fc = c->fc;
     const double tau = c->tau;
+    if (done || !split) return;
     const int32_t nxt = (round + 1) & 1;
     uint2 *next = g.front[nxt];
     uint32_t *nflags = g.flags[nxt];
