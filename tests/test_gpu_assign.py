@@ -171,10 +171,11 @@ def test_trained_network_gain(torch):
     running the full simulation on fewer iterations.  (2) On a congested
     planar graph, the anchored estimate of the next routes' travel times is,
     over five MSA transitions, closer to the simulation than reusing the last
-    simulation (what the loop would do without a model)."""
+    simulation (what the loop would do without a model): by a wide margin
+    where the queues respond to the route changes (a quarter of the
+    demand), narrowly where gridlock noise dominates (full demand)."""
     case("trained network gain: MSA on an 8x8 grid; anchored vs stale on regional at 2%")
-    from paper_2406_08496_amd.assign import WIN, Assignment, agreement
-    from paper_2406_08496_amd.surrogate import EdgeMLP
+    from paper_2406_08496_amd.assign import Assignment, agreement
 
     inst = synth.grid_instance(seed=13, side=8, n_trips=3000, depart_window=1200, len_lo=100, len_hi=300)
     inst.n_steps = 4800
@@ -186,18 +187,32 @@ def test_trained_network_gain(torch):
     assert sur["n_sim"] <= len(plain["hist"]) // 2
     assert g <= 0.02
 
-    reg = synth.regional(0.02)
+    for demand, bar in ((0.25, 0.8), (1.0, 0.97)):
+        e_anc, e_stale = anchored_vs_stale(torch, synth.regional(0.02, demand))
+        print(f"regional 2%, demand x{demand}: anchored", e_anc, "stale", e_stale, flush=True)
+        assert np.mean(e_anc) < bar * np.mean(e_stale)
+        if demand < 1.0:
+            assert sum(a < b for a, b in zip(e_anc, e_stale)) >= 4
+
+
+def anchored_vs_stale(torch, reg, n=5):
+    """Errors of the anchored estimate and of the last simulation against
+    the simulation of the next routes, over n MSA transitions, with the
+    perceptron trained on the simulations so far (the last three)."""
+    from paper_2406_08496_amd.assign import WIN, Assignment
+    from paper_2406_08496_amd.surrogate import EdgeMLP
+
     a = Assignment(reg, n_bins=48)
     routes = [(reg.route_off, reg.route_edges)]
     sims = []
-    for j in range(6):
+    for j in range(n + 1):
         st = a.simulate(*routes[-1])
         sims.append(st)
         routes.append(a.reroute(a.edge_tt_from_stats(st), *routes[-1], j + 1))
     net = EdgeMLP(seed=0)
     buf = []
     e_anc, e_stale = [], []
-    for j in range(5):
+    for j in range(n):
         anc = a.anchor(sims[j], *routes[j])
         _, y, m = a.samples(sims[j])
         assert bool(torch.isfinite(y).all())
@@ -218,5 +233,4 @@ def test_trained_network_gain(torch):
         err = lambda t: float((w * np.abs(t - truth) / truth).sum() / w.sum())
         e_anc.append(err(est))
         e_stale.append(err(a.edge_tt_from_stats(sims[j])))
-    print("regional 2%: anchored", e_anc, "stale", e_stale, flush=True)
-    assert np.mean(e_anc) < 0.97 * np.mean(e_stale)
+    return e_anc, e_stale
