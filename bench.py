@@ -134,6 +134,23 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_cpu():
+    """CPU model and hardware thread count of the host the oracle runs on."""
+    import os
+    import platform
+
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "hardware_threads": os.cpu_count()}
+
+
 def cpu_baseline(inst, n_bins, budget_s, plan=None):
     """The oracle as it is, on the host cores: the single-threaded build from
     step 0 until `budget_s` runs out (whole 100-step blocks), then the
@@ -164,7 +181,8 @@ def cpu_baseline(inst, n_bins, budget_s, plan=None):
            "sample": f"steps 0..{steps} of the same workload ({par['vehicle_steps']} vehicle-steps); "
                      f"all-cores build {par['seconds']:.1f} s on {par['cores']} threads, "
                      f"single-threaded build {one['seconds']:.1f} s",
-           "single_thread": {"value": one["value"], "cores": 1, "seconds": one["seconds"]}}
+           "single_thread": {"value": one["value"], "cores": 1, "seconds": one["seconds"]},
+           "host": host_cpu()}
     return out, steps
 
 
