@@ -418,8 +418,9 @@ int32_t lpsim_router_solve(lpsim_router *r, const double *cost, int64_t n_trips,
  * one pass that picks each node's tree edge.  The trees stay on the device:
  * lpsim_router_fill after this call walks them there and copies the routes
  * back.  `stream` is a hipStream_t or NULL; the call returns when the solve
- * is done.  Device memory for the graph and the trees is kept until
- * lpsim_router_destroy.  Errors: as lpsim_router_solve, and EDEVICE. */
+ * is done.  Device memory for the graph and the trees, and page-locked host
+ * buffers for the routes coming back, are kept until lpsim_router_destroy.
+ * Errors: as lpsim_router_solve, and EDEVICE. */
 int32_t lpsim_router_solve_gpu(lpsim_router *r, const double *cost, int64_t n_trips, const int32_t *origin,
                                const int32_t *dest, void *stream);
 
@@ -444,8 +445,12 @@ int32_t lpsim_edge_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_su
 /* Write the routes of the last solve (host buffers).  take_new (n_trips
  * flags) NULL takes every new route; otherwise trip i keeps its old route
  * (old_off / old_edges) where take_new[i] == 0.  out_off receives n_trips+1
- * offsets; out_edges (may be NULL to size the result first) the edge ids.
- * Errors: ESTATE (no solve), EINVAL. */
+ * offsets; out_edges (may be NULL to size the result first) the edge ids;
+ * out_edges must not overlap old_edges.  After a GPU solve, a call that
+ * follows a sizing call for the same take_new contents reuses its route
+ * lengths instead of walking the trees again.
+ * Errors: ESTATE (no solve), EINVAL; after a GPU solve also ENOMEM and
+ * EDEVICE. */
 int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t *old_edges, const uint8_t *take_new,
                           int64_t *out_off, int32_t *out_edges);
 
