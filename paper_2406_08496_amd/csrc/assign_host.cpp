@@ -140,6 +140,16 @@ void prefix_sum(int64_t n, int32_t n_threads, int64_t *out, F &&len_of) {
     });
 }
 
+// the new routes' buffer shares memory with the old routes' (which the
+// fill still reads)
+bool routes_overlap(const int64_t *old_off, const int32_t *old_edges, const int64_t *out_off,
+                    const int32_t *out_edges, int64_t n) {
+    if (!old_edges || !out_edges) return false;
+    const uintptr_t ob = (uintptr_t)old_edges, oe = ob + (uintptr_t)old_off[n] * 4;
+    const uintptr_t nb = (uintptr_t)out_edges, ne = nb + (uintptr_t)out_off[n] * 4;
+    return nb < oe && ob < ne;
+}
+
 }  // namespace
 
 extern "C" {
@@ -335,6 +345,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
             return !take_new || take_new[i] ? len[i] : old_off[i + 1] - old_off[i];
         });
         if (!out_edges) return LPSIM_OK;
+        if (take_new && routes_overlap(old_off, old_edges, out_off, out_edges, n)) return LPSIM_EINVAL;
         // the new routes come back packed (page-locked), the old ones are
         // copied on the host
         int64_t *poff = lpsim_route::gpu_router_offsets(r->gpu);
@@ -379,6 +390,7 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
         });
     }
     if (!out_edges) return LPSIM_OK;
+    if (take_new && routes_overlap(old_off, old_edges, out_off, out_edges, n)) return LPSIM_EINVAL;
     parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
         for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i) {
             int32_t *o = out_edges + out_off[i];

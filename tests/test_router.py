@@ -150,6 +150,36 @@ def test_routes_into_a_reused_buffer():
     assert np.array_equal(c[0], c_want[0]) and np.array_equal(c[1], c_want[1])
 
 
+def test_fill_refuses_to_overwrite_the_old_routes():
+    """Writing the new routes over the old routes' memory, which the fill
+    still reads, is an argument error (nothing is written)."""
+    inst = synth.grid_instance(seed=6, side=6, n_trips=200)
+    cost = (inst.length / inst.speed).astype(np.float64) * 1.5
+    origin = np.ascontiguousarray(inst.meta["origin"], np.int32)
+    dest = np.ascontiguousarray(inst.meta["dest"], np.int32)
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=2)
+    take = (np.arange(inst.n_trips) % 2 == 0).astype(np.uint8)
+    old_off = np.ascontiguousarray(inst.route_off, np.int64)
+    buf = np.zeros(int(old_off[-1]) * 2 + 64, np.int32)
+    buf[:old_off[-1]] = inst.route_edges
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    c = np.ascontiguousarray(cost)
+    assert r.lib.lpsim_router_solve(r._h, vp(c), inst.n_trips, vp(origin), vp(dest)) == 0
+    off = np.zeros(inst.n_trips + 1, np.int64)
+    assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), None) == 0
+    keep = buf.copy()
+    # out_edges starting inside the old routes
+    out = buf[10:]
+    assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), vp(out)) != 0
+    assert np.array_equal(buf, keep)
+    # the spare space after them is fine
+    out = buf[int(old_off[-1]):]
+    assert off[-1] <= len(out)
+    assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), vp(out)) == 0
+    want = r.routes(cost, origin, dest, old=(old_off, inst.route_edges.copy()), take_new=take)
+    assert np.array_equal(off, want[0]) and np.array_equal(out[:off[-1]], want[1])
+
+
 def test_msa_switch_definition():
     """lpsim_msa_switch against its definition written out with Python
     integers: SplitMix64 of seed ^ i << 8 ^ n, modulo n + 1."""
