@@ -449,8 +449,8 @@ int32_t lpsim_edge_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_su
  * out_edges must not overlap old_edges.  After a GPU solve, a call that
  * follows a sizing call for the same take_new contents reuses its route
  * lengths instead of walking the trees again.
- * Errors: ESTATE (no solve), EINVAL; after a GPU solve also ENOMEM and
- * EDEVICE. */
+ * Errors: ESTATE (no solve), EINVAL (also for old offsets that decrease
+ * over a kept route); after a GPU solve also ENOMEM and EDEVICE. */
 int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t *old_edges, const uint8_t *take_new,
                           int64_t *out_off, int32_t *out_edges);
 

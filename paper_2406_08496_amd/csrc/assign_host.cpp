@@ -321,6 +321,15 @@ int32_t lpsim_router_fill(lpsim_router *r, const int64_t *old_off, const int32_t
     if (take_new && (!old_off || !old_edges)) return LPSIM_EINVAL;
     const int64_t chunk = 65536;
     const int32_t n_chunks = (int32_t)((n + chunk - 1) / chunk);
+    if (take_new) {
+        // the old routes that are kept must have non-negative lengths
+        std::atomic<bool> bad{false};
+        parallel_for(n_chunks, r->n_threads, [&](int32_t ci) {
+            for (int64_t i = ci * chunk; i < std::min<int64_t>(n, (ci + 1) * chunk); ++i)
+                if (!take_new[i] && old_off[i + 1] < old_off[i]) bad.store(true, std::memory_order_relaxed);
+        });
+        if (bad.load()) return LPSIM_EINVAL;
+    }
     if (r->on_gpu) {
         // lengths of the new routes from walks on the device; a call that
         // follows a sizing call for the same choice of trips reuses them

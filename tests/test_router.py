@@ -152,7 +152,8 @@ def test_routes_into_a_reused_buffer():
 
 def test_fill_refuses_to_overwrite_the_old_routes():
     """Writing the new routes over the old routes' memory, which the fill
-    still reads, is an argument error (nothing is written)."""
+    still reads, is an argument error (nothing is written), and so are old
+    offsets that run backwards for a route that is kept."""
     inst = synth.grid_instance(seed=6, side=6, n_trips=200)
     cost = (inst.length / inst.speed).astype(np.float64) * 1.5
     origin = np.ascontiguousarray(inst.meta["origin"], np.int32)
@@ -172,7 +173,13 @@ def test_fill_refuses_to_overwrite_the_old_routes():
     out = buf[10:]
     assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), vp(out)) != 0
     assert np.array_equal(buf, keep)
+    # old offsets that run backwards for a kept route
+    bad_off = old_off.copy()
+    k = int(np.nonzero(take == 0)[0][0])
+    bad_off[k + 1] = bad_off[k] - 1
+    assert r.lib.lpsim_router_fill(r._h, vp(bad_off), vp(buf), vp(take), vp(off), None) != 0
     # the spare space after them is fine
+    assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), None) == 0
     out = buf[int(old_off[-1]):]
     assert off[-1] <= len(out)
     assert r.lib.lpsim_router_fill(r._h, vp(old_off), vp(buf), vp(take), vp(off), vp(out)) == 0
