@@ -215,6 +215,16 @@ int32_t lpsim_edge_stats(lpsim_ctx *ctx, int64_t *tt_sum_steps, int32_t *n_exits
                          int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
                          int64_t *occ_steps_bin);
 
+/* The binned statistics of lpsim_edge_stats, the same values in the same
+ * [E*B] input-edge-order layout, written into DEVICE buffers (caller-owned,
+ * any may be NULL) by kernels queued on `stream` (a hipStream_t, or NULL for
+ * the context's own stream) after the steps already queued; nothing crosses
+ * to the host and the call does not wait.  For callers that feed the
+ * statistics to device work (the surrogate's features and targets).
+ * Errors: ESTATE, EDEVICE. */
+int32_t lpsim_edge_stats_device(lpsim_ctx *ctx, int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
+                                int64_t *occ_steps_bin, void *stream);
+
 /* Vehicle positions and speeds: the output of Algorithm 1 (vehicle position
  * P and speed v), with the current edge and lane that Section 3.1 (vehicle
  * data) keeps per vehicle and the lane-map cell it marks.
@@ -441,6 +451,12 @@ int32_t lpsim_edge_tt(int32_t n_edges, const int64_t *tt_sum_steps, const int32_
  * traversal entered in the bin (host arrays). */
 int32_t lpsim_edge_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum_bin, const int32_t *exits_bin,
                            const double *tt_free_steps, float *out_steps);
+
+/* lpsim_edge_tt_bins on device arrays, queued on `stream` (hipStream_t or
+ * NULL): the same float64 quotient rounded once, so the same values.
+ * Errors: EINVAL, EDEVICE. */
+int32_t lpsim_edge_tt_bins_device(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum_bin, const int32_t *exits_bin,
+                                  const double *tt_free_steps, float *out_steps, void *stream);
 
 /* Write the routes of the last solve (host buffers).  take_new (n_trips
  * flags) NULL takes every new route; otherwise trip i keeps its old route

@@ -149,7 +149,8 @@ class Assignment:
         self.sim.step(self.horizon)
         self.torch.cuda.synchronize()
         t2 = time.perf_counter()
-        st = self.sim.edge_stats(binned=binned)
+        # the binned statistics feed only device work: they stay there
+        st = self.sim.edge_stats(binned=binned, device=binned)
         t3 = time.perf_counter()
         self._add("simulate", t3 - t0)
         self._add("sim_load", t1 - t0)
@@ -235,6 +236,7 @@ class Assignment:
             lanes=torch.from_numpy(inst.lanes.astype(np.uint8)).to(dev),
             speed=torch.from_numpy(inst.speed.astype(np.float32)).to(dev),
             tt_free=torch.from_numpy(self.tt_free.astype(np.float32)).to(dev),
+            tt_free64=torch.from_numpy(np.ascontiguousarray(self.tt_free, np.float64)).to(dev),
             dep=torch.from_numpy(inst.depart_step.astype(np.int32)).to(dev),
             jam=float(self.sim.params["veh_len"] + self.sim.params["s0"]),
         )
@@ -268,7 +270,7 @@ class Assignment:
         nw = B // WIN
         # device copies held in locals until the kernels have been enqueued
         # (a temporary freed early would let the next copy reuse its memory)
-        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        d = lambda a: a if torch.is_tensor(a) else torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
         inflow_d, occ_d = d(st["inflow_bin"]), d(st["occ_bin"])
         exits_d, ttb_d = d(st["exits_bin"]), d(st["tt_bin"])
         x = self.features(inflow_d, occ_d)
@@ -336,6 +338,14 @@ class Assignment:
         """Per-(edge, bin) mean travel time in steps, free flow where no
         traversal entered (device, float32)."""
         E, B = st["tt_bin"].shape
+        if self.torch.is_tensor(st["tt_bin"]):
+            sd = self._surrogate_setup()
+            out = self.torch.empty((E, B), dtype=self.torch.float32, device="cuda")
+            rc = sd["lib"].lpsim_edge_tt_bins_device(E, B, self._vp(st["tt_bin"]), self._vp(st["exits_bin"]),
+                                                     self._vp(sd["tt_free64"]), self._vp(out), sd["stream"])
+            if rc:
+                raise LpsimError(rc, "edge tt bins")
+            return out
         out = np.empty((E, B), np.float32)
         tf = np.ascontiguousarray(self.tt_free, np.float64)
         rc = load_library().lpsim_edge_tt_bins(E, B, _p(np.ascontiguousarray(st["tt_bin"], np.int64)),

@@ -11,7 +11,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblpsim.so")
 
 SOURCES = ["lpsim_kernels.hip", "lpsim_host.cpp", "mlp_kernels.hip", "mlp_host.cpp",
-           "surrogate_kernels.hip", "assign_host.cpp", "router_kernels.hip"]
+           "surrogate_kernels.hip", "assign_host.cpp", "router_kernels.hip", "stats_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -218,6 +218,12 @@ void launch_lanechg(const Dev &d, int blocks, int threads, hipStream_t s, Kernel
 constexpr uint32_t END_HELPERS = 8;
 void launch_commit(const Dev &d, int blocks, int threads, hipStream_t s, KernelEvents ev = {});
 void launch_reorder(const Dev &d, int blocks, int threads, hipStream_t s);
+// binned statistics in input edge order into device arrays (any may be
+// NULL), the occupancy completed for the vehicles still on an edge; `ct` is
+// the current control block, `ext` maps internal to input edge ids
+hipError_t launch_stats_device(const Dev &d, const Ctrl *ct, const int32_t *ext, int32_t E, int32_t B,
+                               int32_t bin_steps, uint32_t slot_cap, int32_t *inflow, int32_t *exits,
+                               unsigned long long *tt, unsigned long long *occ, hipStream_t s);
 constexpr int SORT_CHUNK = 4096;  // edges per scan block
 
 }  // namespace lpsim

@@ -46,6 +46,7 @@ struct lpsim_ctx {
     std::vector<int32_t> look;                 // per scenario lookahead D
     std::vector<int32_t> ext_of_int;           // internal edge -> global input edge id
     std::vector<int32_t> int_of_ext;           // global input edge id -> internal
+    int32_t *ext_d = nullptr;                  // ext_of_int on the device
     std::vector<int32_t> src_g, dst_g;         // global input edge order, local node ids
     std::vector<uint32_t> aux_h;               // internal order
     uint2 *sig_d = nullptr;                    // signal words (allocated on first use)
@@ -222,6 +223,7 @@ static void release_trips(lpsim_ctx *c) {
 static void release_net(lpsim_ctx *c) {
     release_trips(c);
     dev_free_all(c, c->net_allocs);
+    c->ext_d = nullptr;
     c->sig_d = nullptr;
     c->d.sig = nullptr;
     c->have_net = false;
@@ -356,6 +358,7 @@ static int32_t build_network(lpsim_ctx *c, const NetIn &in) {
     if ((rc = upload(c, *(int32_t **)&escen_d, escen.data(), escen.size(), c->net_allocs))) return rc;
     d.escen = escen_d;
     d.n_scen = S;
+    if ((rc = upload(c, c->ext_d, ext_of_int.data(), ext_of_int.size(), c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.map, off + 256, c->net_allocs))) return rc;
     if ((rc = alloc_n(c, d.claims, (size_t)slot, c->net_allocs))) return rc;
     const size_t nb = (size_t)E * (size_t)c->dp.n_bins;
@@ -1142,6 +1145,23 @@ int32_t lpsim_edge_stats(lpsim_ctx *c, int64_t *tt_sum_steps, int32_t *n_exits, 
         }
         perm_rows(occ_steps_bin, t, B);
     }
+    return LPSIM_OK;
+}
+
+int32_t lpsim_edge_stats_device(lpsim_ctx *c, int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
+                                int64_t *occ_steps_bin, void *hip_stream) {
+    int32_t rc = check_ready(c, true);
+    if (rc) return rc;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->own;
+    if (c->last && c->last != s) {
+        // the steps queued on another stream come first
+        HIPCHK(c, hipEventRecord(c->order_ev, c->last));
+        HIPCHK(c, hipStreamWaitEvent(s, c->order_ev, 0));
+    }
+    c->last = s;
+    HIPCHK(c, launch_stats_device(c->d, c->d.ctrl + (c->k & 1), c->ext_d, c->n_edges, c->dp.n_bins,
+                                  c->dp.bin_steps, c->slot_cap, inflow_bin, exits_bin,
+                                  (unsigned long long *)tt_sum_bin, (unsigned long long *)occ_steps_bin, s));
     return LPSIM_OK;
 }
 

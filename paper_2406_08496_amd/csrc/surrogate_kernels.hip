@@ -152,6 +152,15 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
+// mean travel time per (edge, bin) in steps: the float64 quotient rounded
+// once to float32, or the edge's free-flow time where nothing entered
+__global__ void k_tt_bins(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum, const int32_t *exits,
+                          const double *tt_free, float *out) {
+    const int64_t n = (int64_t)n_edges * n_bins;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = exits[i] > 0 ? (float)((double)tt_sum[i] / (double)exits[i]) : (float)tt_free[i / n_bins];
+}
+
 }  // namespace lpsim_sur
 
 using namespace lpsim_sur;
@@ -172,6 +181,17 @@ int32_t lpsim_surrogate_load(const int64_t *route_off, const int32_t *route_edge
     if (n_trips == 0) return LPSIM_OK;
     hipLaunchKernelGGL(k_load, dim3(grid_for(n_trips)), dim3(256), 0, s, route_off, route_edges, depart_step, n_trips,
                        tt_steps, n_bins, bin_steps, horizon, inflow_bin, (unsigned long long *)occ_steps_bin);
+    return hipGetLastError() == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE;
+}
+
+int32_t lpsim_edge_tt_bins_device(int32_t n_edges, int32_t n_bins, const int64_t *tt_sum_bin, const int32_t *exits_bin,
+                                  const double *tt_free_steps, float *out_steps, void *stream) {
+    if (n_edges < 0 || n_bins < 1 || (n_edges > 0 && (!tt_sum_bin || !exits_bin || !tt_free_steps || !out_steps)))
+        return LPSIM_EINVAL;
+    if (n_edges == 0) return LPSIM_OK;
+    const int64_t n = (int64_t)n_edges * n_bins;
+    hipLaunchKernelGGL(k_tt_bins, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n_edges, n_bins, tt_sum_bin,
+                       exits_bin, tt_free_steps, out_steps);
     return hipGetLastError() == hipSuccess ? LPSIM_OK : LPSIM_EDEVICE;
 }
 

@@ -66,6 +66,7 @@ SIGNATURES = {
     "lpsim_step": ([_vp, _i32, _vp], _i32),
     "lpsim_prepare_steps": ([_vp, _i32], _i32),
     "lpsim_edge_stats": ([_vp] + [_vp] * 6, _i32),
+    "lpsim_edge_stats_device": ([_vp] * 6, _i32),
     "lpsim_get_vehicles": ([_vp] + [_vp] * 7, _i32),
     "lpsim_get_counters": ([_vp, ctypes.POINTER(Counters)], _i32),
     "lpsim_block_edge": ([_vp, _i32, _i32], _i32),
@@ -85,6 +86,7 @@ SIGNATURES = {
     "lpsim_msa_switch": ([_i64, _i32, ctypes.c_uint64, _vp], _i32),
     "lpsim_edge_tt": ([_i32, _vp, _vp, _vp, ctypes.c_double, _vp], _i32),
     "lpsim_edge_tt_bins": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
+    "lpsim_edge_tt_bins_device": ([_i32, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_router_fill": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_load": ([_vp, _vp, _vp, _i64, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp], _i32),
     "lpsim_surrogate_features": ([_i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
@@ -283,15 +285,31 @@ class Simulator:
             "edge", "lane", "cell", "x", "v", "arrival_step", "status")]))
         return out
 
-    def edge_stats(self, binned=True):
+    def edge_stats(self, binned=True, device=False):
+        """Per-edge statistics in input edge order (lpsim_edge_stats).  With
+        device=True the binned arrays are torch tensors on the GPU, written
+        by kernels queued on the current stream (lpsim_edge_stats_device);
+        the unbinned ones are host arrays either way."""
         E, B = self.n_edges, self.params["n_bins"]
         out = dict(tt_sum=np.empty(E, np.int64), n_exits=np.empty(E, np.int32))
-        if binned:
+        if binned and not device:
             out.update(inflow_bin=np.empty((E, B), np.int32), exits_bin=np.empty((E, B), np.int32),
                        tt_bin=np.empty((E, B), np.int64), occ_bin=np.empty((E, B), np.int64))
         g = lambda k: _p(out.get(k))
         self._check(load_library().lpsim_edge_stats(self._h, g("tt_sum"), g("n_exits"), g("inflow_bin"),
                                                     g("exits_bin"), g("tt_bin"), g("occ_bin")))
+        if binned and device:
+            import torch
+
+            t = dict(inflow_bin=torch.empty((E, B), dtype=torch.int32, device="cuda"),
+                     exits_bin=torch.empty((E, B), dtype=torch.int32, device="cuda"),
+                     tt_bin=torch.empty((E, B), dtype=torch.int64, device="cuda"),
+                     occ_bin=torch.empty((E, B), dtype=torch.int64, device="cuda"))
+            vp = lambda k: ctypes.c_void_p(t[k].data_ptr())
+            self._check(load_library().lpsim_edge_stats_device(
+                self._h, vp("inflow_bin"), vp("exits_bin"), vp("tt_bin"), vp("occ_bin"),
+                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+            out.update(t)
         return out
 
     def counters(self):

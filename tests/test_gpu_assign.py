@@ -132,6 +132,34 @@ def test_shift_and_edge_tt(torch):
                                      ctypes.c_float(1000.0), vp(out), None) != 0
 
 
+def test_device_stats_equal_host(torch):
+    """The binned statistics handed over on the device (lpsim_edge_stats_device)
+    equal the host copies element by element, with vehicles still on their
+    edges (occupancy completed up to the current step) and again later in the
+    run; the per-bin travel times computed from them on the device
+    (lpsim_edge_tt_bins_device) equal the host routine's."""
+    from paper_2406_08496_amd.assign import Assignment
+
+    inst = synth.grid_instance(seed=13, side=8, n_trips=3000, depart_window=1200, len_lo=100, len_hi=300)
+    a = Assignment(inst, n_bins=24)
+    a.sim.load_trips(inst.depart_step, inst.route_off, inst.route_edges)
+    for steps in (700, 900):
+        a.sim.step(steps)
+        host = a.sim.edge_stats(binned=True)
+        dev = a.sim.edge_stats(binned=True, device=True)
+        case("device statistics vs host after", steps, "more steps,", a.sim.counters()["vehicle_steps"],
+             "vehicle-steps")
+        assert np.array_equal(host["tt_sum"], dev["tt_sum"]) and np.array_equal(host["n_exits"], dev["n_exits"])
+        for k in ("inflow_bin", "exits_bin", "tt_bin", "occ_bin"):
+            assert torch.is_tensor(dev[k])
+            got = dev[k].cpu().numpy()
+            assert got.dtype == host[k].dtype and np.array_equal(got, host[k]), k
+        assert host["occ_bin"].sum() > 0 and host["exits_bin"].sum() > 0
+        tb_h = a.tt_bins_from_stats(host).cpu().numpy()
+        tb_d = a.tt_bins_from_stats(dev).cpu().numpy()
+        assert np.array_equal(tb_h.view(np.uint32), tb_d.view(np.uint32))
+
+
 def test_msa_small_end_to_end(torch):
     case("MSA, 6 iterations, plain vs surrogate, 8x8 grid")
     from paper_2406_08496_amd.assign import Assignment, agreement
