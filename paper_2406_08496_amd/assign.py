@@ -282,15 +282,25 @@ class Assignment:
             raise LpsimError(rc, "targets")
         return x, y, m
 
+    def routes_to_device(self, off, edges):
+        """Device copies of routes (offsets int64, edge ids int32), for
+        several loadings of the same routes."""
+        torch = self.torch
+        return (torch.from_numpy(np.ascontiguousarray(off, np.int64)).to("cuda"),
+                torch.from_numpy(np.ascontiguousarray(edges, np.int32)).to("cuda"))
+
     def load(self, off, edges, tt_bins):
-        """Network loading of routes under per-(edge, bin) travel times
-        (device, steps): (inflow, occupancy) on the device."""
+        """Network loading of routes (host arrays, or device tensors from
+        routes_to_device) under per-(edge, bin) travel times (device, steps):
+        (inflow, occupancy) on the device."""
         torch = self.torch
         sd = self._surrogate_setup()
         E, B = self.inst.n_edges, self.n_bins
         vp = self._vp
-        off_d = torch.from_numpy(np.ascontiguousarray(off, np.int64)).to("cuda")
-        edges_d = torch.from_numpy(np.ascontiguousarray(edges, np.int32)).to("cuda")
+        if torch.is_tensor(off):
+            off_d, edges_d = off, edges
+        else:
+            off_d, edges_d = self.routes_to_device(off, edges)
         inflow_d = torch.empty((E, B), dtype=torch.int32, device="cuda")
         occ_d = torch.empty((E, B), dtype=torch.int64, device="cuda")
         rc = sd["lib"].lpsim_surrogate_load(vp(off_d), vp(edges_d), vp(sd["dep"]), len(self.origin), vp(tt_bins),
@@ -385,9 +395,14 @@ class Assignment:
             if anc is None or judge or not use_sur:
                 rec = {"n": n, "mode": "sim"}
                 est = None
+                # the judge's estimate and the new anchor load the same
+                # routes: one upload serves both
+                ts = time.perf_counter()
+                rd = self.routes_to_device(off, edges)
+                self._add("routes_up", time.perf_counter() - ts)
                 if anc is not None:
                     ts = time.perf_counter()
-                    est = self.estimate(net, anc, off, edges, max_shift)
+                    est = self.estimate(net, anc, *rd, max_shift)
                     self._add("surrogate", time.perf_counter() - ts)
                 st = self.simulate(off, edges)
                 tt = self.edge_tt_from_stats(st)
@@ -403,7 +418,8 @@ class Assignment:
                     # what reusing the previous simulation would have scored
                     rec["stale_mean_rel"], rec["stale_rel_l2"] = edge_tt_errors(prev_tt, tt, w)
                 prev_tt = tt
-                anc = self.anchor(st, off, edges)
+                anc = self.anchor(st, *rd)
+                del rd
                 _, y, m = self.samples(st)
                 keep = m[:, :WIN].any(dim=1)
                 buf.append((anc["x"][keep], y[keep], m[keep]))
