@@ -187,6 +187,26 @@ def test_fill_refuses_to_overwrite_the_old_routes():
     assert np.array_equal(off, want[0]) and np.array_equal(out[:off[-1]], want[1])
 
 
+def test_fill_over_many_chunks():
+    """More trips than one chunk of the fill's parallel prefix sums (65,536):
+    the offsets equal a plain cumulative sum of the route lengths (new routes
+    where taken, old ones elsewhere) and every route is where they say."""
+    from paper_2406_08496_amd.assign import msa_switch
+
+    inst = synth.grid_instance(seed=9, side=7, n_trips=150_000)
+    o, d = inst.meta["origin"], inst.meta["dest"]
+    r = Router(inst.n_nodes, inst.src, inst.dst, n_threads=4)
+    cost = (inst.length / inst.speed).astype(np.float64) * np.linspace(1.0, 3.0, inst.n_edges)
+    take = msa_switch(inst.n_trips, 2, 0x5EED)
+    off, edges = r.routes(cost, o, d, old=(inst.route_off, inst.route_edges), take_new=take)
+    new_off, new_edges = r.routes(cost, o, d)
+    lens = np.where(take == 1, np.diff(new_off), np.diff(inst.route_off))
+    assert off[0] == 0 and np.array_equal(off[1:], np.cumsum(lens))
+    for i in list(range(0, inst.n_trips, 9973)) + [65535, 65536, 131072, inst.n_trips - 1]:
+        want = new_edges[new_off[i]:new_off[i + 1]] if take[i] else inst.route_edges[inst.route_off[i]:inst.route_off[i + 1]]
+        assert np.array_equal(edges[off[i]:off[i + 1]], want), i
+
+
 def test_msa_switch_definition():
     """lpsim_msa_switch against its definition written out with Python
     integers: SplitMix64 of seed ^ i << 8 ^ n, modulo n + 1."""
