@@ -220,8 +220,9 @@ int32_t lpsim_edge_stats(lpsim_ctx *ctx, int64_t *tt_sum_steps, int32_t *n_exits
  * any may be NULL) by kernels queued on `stream` (a hipStream_t, or NULL for
  * the context's own stream) after the steps already queued; nothing crosses
  * to the host and the call does not wait.  For callers that feed the
- * statistics to device work (the surrogate's features and targets).
- * Errors: ESTATE, EDEVICE. */
+ * statistics to device work (the surrogate's features and targets).  A
+ * later load of trips or of a network, and lpsim_destroy, wait for these
+ * kernels.  Errors: ESTATE, EDEVICE. */
 int32_t lpsim_edge_stats_device(lpsim_ctx *ctx, int32_t *inflow_bin, int32_t *exits_bin, int64_t *tt_sum_bin,
                                 int64_t *occ_steps_bin, void *stream);
 

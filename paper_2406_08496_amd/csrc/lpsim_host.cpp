@@ -214,6 +214,10 @@ static void rcb(std::vector<int32_t> &idx, size_t lo, size_t hi, const float *xy
 // network
 
 static void release_trips(lpsim_ctx *c) {
+    // work still queued on the context's streams may read what is freed
+    // here (steps, or statistics handed over on the device)
+    if (c->last) (void)hipStreamSynchronize(c->last);
+    if (c->own) (void)hipStreamSynchronize(c->own);
     drop_graphs(c);
     dev_free_all(c, c->trip_allocs);
     c->have_trips = false;
