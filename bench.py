@@ -276,7 +276,7 @@ def main():
         summarize_profile(args.summarize_profile, args.steps or 20)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the simulator runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
